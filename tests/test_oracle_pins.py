@@ -1,0 +1,422 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names the passage of the paper it pins and the kind of pin: a
+closed form, a special case that reduces to a library routine, brute force on
+tiny inputs, or an invariant.  None of these calls the HIP library.
+"""
+import glob
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def const_image(dims, C, value, dtype=np.uint8):
+    return np.full(tuple(dims[::-1]) + (C,), value, dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+# Grid (Sec. 2.2 / 3.1 stage 1)
+
+def test_grid_counts_of_the_workloads():
+    """The superpixel counts stated for the three single-image workloads."""
+    assert oracle.num_clusters([256, 256], [16, 16])[0] == 256
+    assert oracle.num_clusters([16384, 16384], [16, 16])[0] == 1048576
+    assert oracle.num_clusters([1024, 1024, 1024], [8, 8, 8])[0] == 2097152
+
+
+@pytest.mark.parametrize("S", [4, 5, 8, 12, 16])
+def test_grid_seeds_cover_every_voxel(S):
+    """On a constant image the centres are the grid seeds (no gradient).  With
+    S >= 4 every voxel is within S-1 of a seed on every axis, so even after a
+    +-1 move the first assignment reaches every voxel."""
+    for N in range(8, 201, 7):
+        img = const_image([N, 3], 1, 7)
+        cen = oracle.seed(img, 2, [S, 4])
+        xs = np.unique(cen[:, 1])
+        assert len(xs) == oracle.num_clusters([N], [S])[0]
+        d = np.abs(np.arange(N)[:, None] - xs[None, :]).min(1)
+        assert d.max() <= S - 1
+        # seeds at j*S + S/2 when S divides N (checked against the closed form)
+        if N % S == 0 and S % 2 == 0:
+            np.testing.assert_array_equal(xs, np.arange(N // S) * S + S // 2)
+
+
+# ---------------------------------------------------------------------------
+# P1: constant image, closed form (Sec. 2.1, 2.2, 3.1)
+
+def p1_axis(N, S):
+    """Closed form along one axis: label index and centre of every voxel."""
+    K = N // S
+    x = np.arange(N)
+    j = np.where(x <= S, 0, (x - 1) // S)
+    c = np.array([S / 2] + [jj * S + (S + 1) / 2 for jj in range(1, K - 1)]
+                 + [(K - 1) * S + S / 2])
+    return j, c
+
+
+@pytest.mark.parametrize("dims,S,C", [((64, 48), (16, 8), 3), ((48, 40, 32), (8, 8, 8), 1),
+                                      ((96, 32), (8, 16), 2)])
+def test_p1_constant_image_closed_form(dims, S, C):
+    img = const_image(dims, C, 123)
+    r = oracle.run(img, len(dims), S, 10.0, 4, connectivity=True)
+    Ka = [d // s for d, s in zip(dims, S)]
+    js, cs = zip(*[p1_axis(d, s) for d, s in zip(dims, S)])
+    X = brute.coords(dims)
+    exp = np.zeros(X.shape[0], dtype=np.int64)
+    st = 1
+    for i in range(len(dims)):
+        exp += js[i][X[:, i]] * st
+        st *= Ka[i]
+    np.testing.assert_array_equal(r["labels"], exp)
+    # centres: separable closed form, value = the constant
+    K = int(np.prod(Ka))
+    grid = np.stack(np.meshgrid(*[cs[i] for i in range(len(dims))], indexing="ij"), -1)
+    grid = grid.reshape(-1, len(dims), order="F")
+    np.testing.assert_array_equal(r["centres"][:, C:], grid)
+    np.testing.assert_array_equal(r["centres"][:, :C], np.full((K, C), 123.0))
+    # labels are a fixed point from the first iteration on
+    assert r["residuals"][0] > 0
+    np.testing.assert_array_equal(r["residuals"][1:], 0.0)
+    assert r["n_labels"] == K
+
+
+# ---------------------------------------------------------------------------
+# P2: grid-aligned piecewise-constant image (labels equal the regions)
+
+@pytest.mark.parametrize("dims,S", [((48, 36), (8, 6)), ((36, 24, 24), (6, 6, 8))])
+def test_p2_grid_aligned_regions(dims, S):
+    rng = np.random.default_rng(2)
+    n = len(dims)
+    Ka = [d // s for d, s in zip(dims, S)]
+    K = int(np.prod(Ka))
+    X = brute.coords(dims)
+    cell = np.zeros(X.shape[0], dtype=np.int64)
+    st = 1
+    for i in range(n):
+        cell += (X[:, i] // S[i]) * st
+        st *= Ka[i]
+    # distinct values 25 apart: every pair differs by more than n*m^2 in square
+    cols = rng.permutation(np.arange(1, K + 1) * 25)[:, None].astype(np.uint16)
+    img = cols[cell].reshape(tuple(dims[::-1]) + (1,))
+    r = oracle.run(img, n, S, 10.0, 3, connectivity=True)
+    np.testing.assert_array_equal(r["labels"], cell)
+    exp_c = np.stack(np.meshgrid(*[np.arange(k) * s + (s - 1) / 2 for k, s in zip(Ka, S)],
+                                 indexing="ij"), -1).reshape(-1, n, order="F")
+    np.testing.assert_array_equal(r["centres"][:, 1:], exp_c)
+    np.testing.assert_array_equal(r["centres"][:, 0], cols[:, 0].astype(np.float64))
+    assert r["n_labels"] == K
+    np.testing.assert_array_equal(r["residuals"][1:], 0.0)
+
+
+def test_p2b_region_unions_are_respected():
+    """Regions made of random unions of grid cells, each a distinct colour: no
+    superpixel crosses a region boundary and every region is exactly a union
+    of superpixels."""
+    rng = np.random.default_rng(5)
+    dims, S, m = (64, 64), (8, 8), 10.0
+    X = brute.coords(dims)
+    # 4x4 coarse blocks of 2x2 cells, random region ids, distinct colours
+    reg_of_block = rng.integers(0, 6, size=(4, 4))
+    reg = reg_of_block[X[:, 1] // 16, X[:, 0] // 16]
+    colours = np.array([[0, 0, 0], [250, 0, 0], [0, 250, 0], [0, 0, 250],
+                        [250, 250, 0], [0, 250, 250]], dtype=np.uint8)
+    img = colours[reg].reshape(64, 64, 3)
+    r = oracle.run(img, 2, S, m, 10, connectivity=False)
+    lab = r["labels"]
+    for k in np.unique(lab):
+        assert len(np.unique(reg[lab == k])) == 1
+
+
+# ---------------------------------------------------------------------------
+# P3: windows cover the image -> textbook k-means assignment (cdist + argmin)
+
+@pytest.mark.parametrize("dims,C,dtype", [((40, 30), 3, np.uint8), ((16, 12, 10), 1, np.uint16),
+                                          ((33, 17), 2, np.float32), ((50,), 4, np.uint8)])
+def test_p3_assign_equals_kmeans_when_windows_cover(dims, C, dtype):
+    rng = np.random.default_rng(3)
+    n = len(dims)
+    S = [2 * d for d in dims]          # every window covers the whole image
+    m = float(S[0]) * 0.5              # m/S_0 = 1/4: scaled coordinates stay exact
+    S = [S[0]] * n
+    hi = 255 if dtype == np.uint8 else 1000
+    img = rng.integers(0, hi + 1, size=tuple(dims[::-1]) + (C,)).astype(dtype)
+    for K in (2, 7, 64):
+        cen = np.zeros((K, C + n))
+        cen[:, :C] = np.round(rng.uniform(0, hi, (K, C)) * 64) / 64
+        cen[:, C:] = np.round(rng.uniform(0, 1, (K, n)) * (np.array(dims) - 1) * 64) / 64
+        lab = np.full(int(np.prod(dims)), -1, dtype=np.int32)
+        oracle.assign(img, n, S, m, cen, lab)
+        exp = brute.kmeans_assign(img, dims, S, m, cen)
+        np.testing.assert_array_equal(lab, exp)
+
+
+def test_p3_tie_break_lowest_index():
+    """Two identical centres: every voxel goes to the lower index."""
+    img = const_image((10, 10), 1, 9)
+    cen = np.array([[9.0, 4.0, 4.0], [9.0, 4.0, 4.0], [9.0, 4.0, 4.0]])
+    cen[0, 1] = 100.0  # far away: out of every window
+    lab = np.full(100, 7, dtype=np.int32)
+    oracle.assign(img, 2, [10, 10], 10.0, cen, lab)
+    assert (lab == 1).all()
+
+
+def test_p3_window_is_closed_and_uncovered_voxels_keep_labels():
+    """|x - c| <= S is inside, S + 1 is outside; voxels no window reaches keep
+    their previous label."""
+    img = const_image((30, 1), 1, 0)
+    cen = np.array([[0.0, 10.0, 0.0]])
+    lab = np.full(30, 5, dtype=np.int32)
+    oracle.assign(img, 2, [4, 1], 1.0, cen, lab)
+    exp = np.full(30, 5, dtype=np.int32)
+    exp[6:15] = 0
+    np.testing.assert_array_equal(lab, exp)
+
+
+# P3b: whole windowed run against brute force, integer image
+
+@pytest.mark.parametrize("dims,S,m,C", [((40, 24), (8, 8), 8.0, 3), ((20, 16, 12), (4, 4, 4), 8.0, 1),
+                                        ((37, 29), (8, 8), 16.0, 2)])
+def test_p3b_windowed_run_equals_brute_force(dims, S, m, C):
+    rng = np.random.default_rng(7)
+    n = len(dims)
+    img = rng.integers(0, 256, size=tuple(dims[::-1]) + (C,)).astype(np.uint8)
+    K, Ka = oracle.num_clusters(dims, S)
+    init = np.zeros((K, C + n))
+    # integer centres: some voxels sit exactly on a window edge
+    init[:, :C] = rng.integers(0, 256, (K, C))
+    grid = np.stack(np.meshgrid(*[(np.arange(k) + 0.5) * d / k for k, d in zip(Ka, dims)],
+                                indexing="ij"), -1).reshape(-1, n, order="F")
+    init[:, C:] = np.floor(grid) + rng.integers(-1, 2, (K, n))
+    init[:, C:] = np.clip(init[:, C:], 0, np.array(dims) - 1)
+    T = 5
+    r = oracle.run(img, n, S, m, T, connectivity=False, init_centres=init)
+    lab = brute.grid_cell_labels(dims, Ka)
+    cen = init.copy()
+    for _ in range(T):
+        lab = brute.kmeans_assign(img, dims, S, m, cen, window=True, prev=lab)
+        cen, cnt = brute.bincount_update(img, dims, lab, cen)
+    np.testing.assert_array_equal(r["labels"], lab)
+    np.testing.assert_array_equal(r["centres"], cen)
+    np.testing.assert_array_equal(r["counts"], cnt)
+
+
+def test_p3b_uncovered_voxels_keep_grid_cell_label():
+    """A centre moved far from its cell leaves voxels that no window reaches in
+    the first iteration; they keep the label of their grid cell, and stale
+    distances from an earlier iteration never decide a later one."""
+    rng = np.random.default_rng(9)
+    dims, S, m, C = (32, 32), (4, 4), 4.0, 1
+    img = rng.integers(0, 256, size=(32, 32, 1)).astype(np.uint8)
+    K, Ka = oracle.num_clusters(dims, S)
+    grid = np.stack(np.meshgrid(*[np.arange(k) * 4 + 2.0 for k in Ka], indexing="ij"), -1)
+    init = np.zeros((K, C + 2))
+    init[:, C:] = grid.reshape(-1, 2, order="F")
+    init[:, 0] = rng.integers(0, 256, K)
+    # empty a 3x3 block of cells: their centres jump to the far corner
+    for jy in range(3, 6):
+        for jx in range(3, 6):
+            init[jx + Ka[0] * jy, C:] = (30.0, 30.0)
+    lab0 = brute.grid_cell_labels(dims, Ka)
+    D1 = brute.kmeans_assign(img, dims, S, m, init, window=True, prev=np.full(1024, -1))
+    assert (D1 == -1).any()  # some voxels really are uncovered
+    for T in (1, 3):
+        r = oracle.run(img, 2, S, m, T, connectivity=False, init_centres=init)
+        lab, cen = lab0.copy(), init.copy()
+        for _ in range(T):
+            lab = brute.kmeans_assign(img, dims, S, m, cen, window=True, prev=lab)
+            cen, _ = brute.bincount_update(img, dims, lab, cen)
+        np.testing.assert_array_equal(r["labels"], lab)
+        np.testing.assert_array_equal(r["centres"], cen)
+
+
+# ---------------------------------------------------------------------------
+# P5: update equals numpy.bincount means (Sec. 3.1 stage 2)
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_p5_update_equals_bincount(dtype):
+    rng = np.random.default_rng(11)
+    dims, C, K = (37, 23, 5), 3, 50
+    hi = 255 if dtype == np.uint8 else 60000
+    img = rng.uniform(0, hi, size=(5, 23, 37, C)).astype(dtype)
+    lab = rng.integers(0, K, int(np.prod(dims))).astype(np.int32)
+    lab[lab == 17] = 3  # cluster 17 empty: keeps its centre
+    cen0 = rng.uniform(0, 10, (K, C + 3))
+    cen, cnt, res = oracle.update(img, 3, [4, 4, 4], 10.0, lab, cen0)
+    exp, ecnt = brute.bincount_update(img, dims, lab, cen0)
+    np.testing.assert_array_equal(cnt, ecnt)
+    if dtype == np.float32:
+        np.testing.assert_allclose(cen, exp, rtol=1e-14)
+    else:
+        np.testing.assert_array_equal(cen, exp)
+    np.testing.assert_array_equal(cen[17], cen0[17])
+    # residual: mean over non-empty clusters of the paper's D(old, new)
+    w = np.array([10.0 ** 2 / 16] * 3)
+    e = np.sqrt(((cen[:, :C] - cen0[:, :C]) ** 2).sum(1) + (w * (cen[:, C:] - cen0[:, C:]) ** 2).sum(1))
+    assert res == pytest.approx(e[ecnt > 0].mean(), rel=1e-14)
+
+
+def test_update_float_sums_are_accurate_over_a_wide_range():
+    """float32 images are summed in FP64 with compensation: a cluster holding
+    +1e20, a thousand ones and -1e20 has mean exactly fsum/count."""
+    import math
+    vals = np.array([1e20] + [1.0] * 1000 + [-1e20], dtype=np.float32)
+    img = vals.reshape(1, -1, 1)
+    lab = np.zeros(vals.size, dtype=np.int32)
+    cen, cnt, _ = oracle.update(img, 2, [8, 1], 1.0, lab, np.zeros((1, 3)))
+    assert cen[0, 0] == math.fsum(vals.astype(np.float64)) / vals.size
+
+
+def test_grid_labels_are_the_seed_intervals():
+    """Before the first iteration a voxel carries the index of the grid cell
+    it lies in: cells are the K_i equal real intervals [jN/K, (j+1)N/K), whose
+    integer points start at ceil(jN/K)."""
+    for dims, S in [((37, 23), (8, 5)), ((16, 9, 7), (4, 4, 3)), ((100,), (7,))]:
+        K, Ka = oracle.num_clusters(dims, S)
+        lab = oracle.grid_labels(dims, S)
+        X = brute.coords(dims)
+        exp = np.zeros(X.shape[0], dtype=np.int64)
+        st = 1
+        for i, (d, k) in enumerate(zip(dims, Ka)):
+            edges = -((-np.arange(1, k) * d) // k)  # ceil(j N / K)
+            exp += np.searchsorted(edges, X[:, i], side="right") * st
+            st *= k
+        np.testing.assert_array_equal(lab, exp)
+
+
+def test_update_is_exact_for_integer_images_at_large_sums():
+    """int64 sums: a 1x1 cluster count of 2^20 voxels of value 65535 is exact."""
+    img = np.full((1024, 1024, 1), 65535, dtype=np.uint16)
+    lab = np.zeros(1 << 20, dtype=np.int32)
+    cen, cnt, _ = oracle.update(img, 2, [1024, 1024], 1.0, lab, np.zeros((1, 3)))
+    assert cen[0, 0] == 65535.0 and cnt[0] == 1 << 20
+    assert cen[0, 1] == 511.5 and cen[0, 2] == 511.5
+
+
+# ---------------------------------------------------------------------------
+# P6: planted gradient minima (Sec. 2.2 footnote, Sec. 3.1 stage 1)
+
+@pytest.mark.parametrize("dtype,dims,S", [(np.uint16, (48, 36), (8, 6)),
+                                          (np.float32, (30, 24, 18), (6, 6, 6)),
+                                          (np.uint8, (40, 40), (8, 8))])
+def test_p6_planted_gradient_minima(dtype, dims, S):
+    rng = np.random.default_rng(13)
+    n = len(dims)
+    X = brute.coords(dims)
+    # a ramp along every axis: the gradient is non-zero everywhere
+    step = 1 if dtype == np.uint8 else 10
+    flat = (step * X.sum(1)).astype(np.float64)
+    K, Ka = oracle.num_clusters(dims, S)
+    strides = np.cumprod([1] + list(dims[:-1]))
+    eye = np.eye(n, dtype=int)
+    targets = []
+    for k in range(K):
+        j = np.array(np.unravel_index(k, Ka, order="F"))
+        s = (2 * j + 1) * np.array(dims) // (2 * np.array(Ka))
+        q = s + rng.integers(-1, 2, n)
+        # make the central difference vanish at q along every axis
+        for i in range(n):
+            flat[(q + eye[i]) @ strides] = flat[(q - eye[i]) @ strides]
+        targets.append(q)
+    img = flat.astype(dtype).reshape(tuple(dims[::-1]) + (1,))
+    cen = oracle.seed(img, n, S)
+    q = np.array(targets, dtype=np.float64)
+    np.testing.assert_array_equal(cen[:, 1:], q)
+    np.testing.assert_array_equal(cen[:, 0], flat[(q.astype(int) @ strides)].astype(dtype))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.uint16])
+def test_seed_multichannel_uses_all_channels(dtype):
+    """A minimum planted only in channel 1 (varying along axis 1) of a
+    2-channel image is found."""
+    dims, S = (24, 24), (8, 8)
+    X = brute.coords(dims)
+    ch0 = np.zeros(X.shape[0])
+    ch1 = 10.0 * X[:, 1]
+    # seed (4,4) -> plant in channel 1 at q=(5,3): equalise y-neighbours
+    def L(x, y):
+        return x + 24 * y
+    ch1[L(5, 4)] = ch1[L(5, 2)]
+    img = np.stack([ch0, ch1], 1).astype(dtype).reshape(24, 24, 2)
+    cen = oracle.seed(img, 2, S)
+    assert tuple(cen[0, 2:]) == (5.0, 3.0)
+
+
+# ---------------------------------------------------------------------------
+# P7: connectivity (Sec. 3.1 stage 3)
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "cc_*.json"))))
+def test_p7_connectivity_hand_cases(path):
+    case = json.load(open(path))
+    lab = np.array([[int(v) for v in row.split()] for row in case["labels"]], dtype=np.int32).ravel()
+    exp = np.array([[int(v) for v in row.split()] for row in case["expected"]], dtype=np.int32).ravel()
+    cen = np.array(case["centres"], dtype=np.float64)
+    nl = oracle.connectivity(case["dims"], case["S"], cen, case["C"], lab)
+    np.testing.assert_array_equal(lab, exp)
+    assert nl == case["n_labels"]
+
+
+@pytest.mark.parametrize("dims,S,seed", [((40, 30), (6, 6), 0), ((20, 16, 12), (4, 4, 4), 1),
+                                         ((64, 48), (8, 8), 2)])
+def test_p7_connectivity_invariants(dims, S, seed):
+    """After enforcement every face-connected component is larger than S^n/4
+    unless it holds the origin, and first-pass components are untouched."""
+    rng = np.random.default_rng(seed)
+    n = len(dims)
+    K, Ka = oracle.num_clusters(dims, S)
+    # blocky random labels with salt noise
+    X = brute.coords(dims)
+    lab0 = brute.grid_cell_labels(dims, Ka)
+    noise = rng.random(X.shape[0]) < 0.15
+    lab0[noise] = rng.integers(0, K, noise.sum())
+    cen = np.zeros((K, 1 + n))
+    cen[:, 1:] = rng.uniform(0, 1, (K, n)) * (np.array(dims) - 1)
+    lab = lab0.copy()
+    nl = oracle.connectivity(dims, S, cen, 1, lab)
+    comp, sizes = brute.components(lab, dims)
+    prodS = int(np.prod(S))
+    for cid in np.unique(comp):
+        if comp[0] == cid:
+            continue
+        assert 4 * sizes[cid] > prodS
+    assert lab.max() < nl and lab.min() >= 0
+    # every new label is a single component
+    for v in range(K, nl):
+        assert len(np.unique(comp[lab == v])) == 1
+
+
+# ---------------------------------------------------------------------------
+# P8: k-means fixed point
+
+def test_p8_fixed_point_reproduces_labels():
+    rng = np.random.default_rng(17)
+    dims, S, m = (24, 20), (24, 20), 24.0  # windows cover everything
+    img = rng.integers(0, 256, size=(20, 24, 3)).astype(np.uint8)
+    r = oracle.run(img, 2, S, m, 60, tol=1e-300, connectivity=False)
+    assert r["residuals"][-1] == 0.0 and r["iterations"] < 60
+    lab = np.full(24 * 20, -1, dtype=np.int32)
+    oracle.assign(img, 2, S, m, r["centres"], lab)
+    np.testing.assert_array_equal(lab, r["labels"])
+
+
+# ---------------------------------------------------------------------------
+# P4 on the oracle: invariants of a full run on a workload-shaped image
+
+def test_p4_invariants_on_synthetic_workload():
+    from paper_1806_08741_amd import synth
+    img = synth.workload_image("rgb-256", "cpu", dims=(128, 96)).numpy()
+    r = oracle.run(img, 2, (16, 16), 10.0, 10, connectivity=False)
+    K = r["centres"].shape[0]
+    assert r["counts"].sum() == 128 * 96
+    assert r["labels"].min() >= 0 and r["labels"].max() < K
+    mean, cnt = brute.bincount_update(img, (128, 96), r["labels"], r["centres"])
+    # the last update made every centre the mean of its members
+    np.testing.assert_array_equal(mean, r["centres"])
+    r2 = oracle.run(img, 2, (16, 16), 10.0, 10, connectivity=True)
+    assert r2["labels"].max() < r2["n_labels"]
