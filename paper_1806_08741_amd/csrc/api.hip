@@ -1,0 +1,409 @@
+// api.hip -- the C ABI of libsslic.so (include/sslic.h, include/sslic_steps.h):
+// argument checks, the context's device workspace and the order of launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/sslic.h"
+#include "../../include/sslic_steps.h"
+#include "sslic_internal.h"
+
+using namespace sslic;
+
+struct sslic_ctx {
+  int device = 0;
+  char* ws = nullptr;   // device workspace
+  size_t ws_size = 0;
+  int32_t* host_ints = nullptr;  // pinned staging for *_out scalars
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(SSLIC_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                              \
+  } while (0)
+
+int64_t grid_count(int64_t n, int64_t s) {
+  int64_t k = (2 * n + s) / (2 * s);
+  return k < 1 ? 1 : k;
+}
+
+// Geometry of a request; checks every validity rule of sslic.h.
+int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, const int32_t* S,
+             double m, int64_t K_override) {
+  if (ndim < 1 || ndim > kMaxDim) return fail(SSLIC_EINVAL, "ndim %d outside [1, 4]", ndim);
+  if (!dims || !S) return fail(SSLIC_EINVAL, "dims and S must be given");
+  if (channels < 1 || channels > kMaxChan)
+    return fail(SSLIC_EINVAL, "channels %d outside [1, 8]", channels);
+  if (dtype != kU8 && dtype != kU16 && dtype != kF32) return fail(SSLIC_EINVAL, "unknown dtype %d", dtype);
+  if (!(m > 0.0) || !std::isfinite(m)) return fail(SSLIC_EINVAL, "m must be positive and finite");
+  memset(g, 0, sizeof *g);
+  g->nd_out = ndim;
+  g->nd = ndim < 2 ? 2 : ndim;
+  g->C = channels;
+  g->dtype = dtype;
+  int64_t N = 1, K = 1, nbins = 1, prodS = 1;
+  for (int i = 0; i < kMaxDim; ++i) {
+    int64_t n = i < ndim ? dims[i] : 1;
+    int64_t s = i < ndim ? S[i] : 1;
+    if (n < 1) return fail(SSLIC_EINVAL, "dims[%d] = %lld < 1", i, (long long)n);
+    if (s < 1) return fail(SSLIC_EINVAL, "S[%d] = %lld < 1", i, (long long)s);
+    if (n > (1LL << 31) || s > (1LL << 30)) return fail(SSLIC_EINVAL, "axis %d too large", i);
+    g->n[i] = (int)n;
+    g->st[i] = N;
+    N *= n;
+    if (N >= (1LL << 31)) return fail(SSLIC_EINVAL, "image has 2^31 voxels or more");
+    g->S[i] = (int)s;
+    g->Ka[i] = (int)grid_count(n, s);
+    K *= g->Ka[i];
+    g->nb[i] = (int)((n + s - 1) / s);
+    g->bst[i] = nbins;
+    nbins *= g->nb[i];
+    prodS *= s;
+    double w = (m * m) / ((double)s * (double)s);
+    g->wd[i] = w;
+    g->w[i] = (float)w;
+  }
+  g->N = N;
+  g->K = K_override > 0 ? K_override : K;
+  if (g->K + N >= (1LL << 31)) return fail(SSLIC_EINVAL, "K + N must stay below 2^31");
+  g->nbins = nbins;
+  g->prodS = prodS;
+  g->rs = rec_words(channels, g->nd);
+  g->F = 1 + g->nd + channels;
+  g->row = channels + ndim;
+  return SSLIC_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part, acc, res_acc, flags;
+  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, total;
+};
+
+Layout layout(const Geo& g, int iterations, bool cc) {
+  Layout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o += al(bytes);
+    return at;
+  };
+  L.ctab = put((size_t)g.K * g.rs * 4);
+  L.bin_of = put((size_t)g.K * 4);
+  L.bin_cnt = put((size_t)g.nbins * 4);
+  L.bin_start = put((size_t)(g.nbins + 1) * 4);
+  L.bin_items = put((size_t)g.K * 4);
+  L.scan_part = put((size_t)(g.nbins / 4096 + 2) * 4);
+  L.acc = put((size_t)g.K * g.F * 8);
+  L.res_acc = put((size_t)2 * (iterations > 0 ? iterations : 1) * 8);
+  L.flags = put(64);
+  if (cc) {
+    L.cc_parent = put((size_t)g.N * 4);
+    L.cc_size = put((size_t)g.N * 4);
+    L.cc_final = put((size_t)g.N);
+    L.cc_newlab = put((size_t)g.N * 4);
+    L.cc_part = put((size_t)(g.N / 4096 + 2) * 4);
+  }
+  L.total = o;
+  return L;
+}
+
+int ensure_ws(sslic_ctx* ctx, size_t need) {
+  if (need <= ctx->ws_size) return SSLIC_OK;
+  if (ctx->ws) {
+    // earlier work on any stream may still use the old workspace
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+  }
+  size_t sz = need + (need >> 3);
+  if (hipMalloc((void**)&ctx->ws, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws = nullptr;
+    return fail(SSLIC_ENOMEM, "cannot allocate %zu bytes of device workspace", sz);
+  }
+  ctx->ws_size = sz;
+  return SSLIC_OK;
+}
+
+Iter iter_view(sslic_ctx* ctx, const Layout& L) {
+  Iter it;
+  char* b = ctx->ws;
+  it.ctab = (float*)(b + L.ctab);
+  it.bin_of = (int32_t*)(b + L.bin_of);
+  it.bin_cnt = (int32_t*)(b + L.bin_cnt);
+  it.bin_start = (int32_t*)(b + L.bin_start);
+  it.bin_items = (int32_t*)(b + L.bin_items);
+  it.scan_part = (int32_t*)(b + L.scan_part);
+  it.acc = (uint64_t*)(b + L.acc);
+  it.res_acc = (double*)(b + L.res_acc);
+  it.done = (int32_t*)(b + L.flags);
+  it.iters = it.done + 1;
+  return it;
+}
+
+CCBuf cc_view(sslic_ctx* ctx, const Layout& L) {
+  CCBuf c;
+  char* b = ctx->ws;
+  c.parent = (int32_t*)(b + L.cc_parent);
+  c.size = (int32_t*)(b + L.cc_size);
+  c.final_ = (uint8_t*)(b + L.cc_final);
+  c.newlab = (int32_t*)(b + L.cc_newlab);
+  c.part = (int32_t*)(b + L.cc_part);
+  c.total = (int32_t*)(b + L.flags) + 2;  // flags: done, iters, total, n_labels
+  return c;
+}
+
+int32_t* nlab_slot(sslic_ctx* ctx, const Layout& L) { return (int32_t*)(ctx->ws + L.flags) + 3; }
+
+int select_device(sslic_ctx* ctx) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  return SSLIC_OK;
+}
+
+// Copy device int32 scalars to host outputs (waits for the stream).
+int read_ints(sslic_ctx* ctx, hipStream_t s, const int32_t* dev_a, int32_t* out_a,
+              const int32_t* dev_b, int32_t* out_b) {
+  if (!out_a && !out_b) return SSLIC_OK;
+  if (out_a) HIP_TRY(hipMemcpyAsync(ctx->host_ints, dev_a, 4, hipMemcpyDeviceToHost, s));
+  if (out_b) HIP_TRY(hipMemcpyAsync(ctx->host_ints + 1, dev_b, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (out_a) *out_a = ctx->host_ints[0];
+  if (out_b) *out_b = ctx->host_ints[1];
+  return SSLIC_OK;
+}
+
+// The iteration loop of one image on the context workspace.  Centres are in
+// `cen` (seeded or given) when called.
+int run_iterations(const Geo& g, const Iter& it, const void* image, int iterations, double tol,
+                   int32_t* labels, double* cen, int64_t* counts, double* residuals, hipStream_t s) {
+  HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
+  HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
+  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * iterations, s));
+  HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
+  if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
+  HIP_TRY(launch_prep(g, cen, it, s));
+  for (int t = 0; t < iterations; ++t) {
+    HIP_TRY(launch_bins(g, it, s));
+    HIP_TRY(launch_assign(g, image, it, labels, t == 0, s));
+    HIP_TRY(launch_update(g, image, labels, it, s));
+    HIP_TRY(launch_finalize(g, cen, counts, it, t, t + 1 < iterations, s));
+    HIP_TRY(launch_residual_finish(it, t, tol, residuals, s));
+  }
+  return SSLIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sslic_last_error(void) { return g_err.c_str(); }
+
+int sslic_create(sslic_ctx** out, int device_ordinal) {
+  if (!out) return fail(SSLIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(SSLIC_EDEVICE, "no HIP device available");
+  }
+  if (device_ordinal < 0 || device_ordinal >= n)
+    return fail(SSLIC_EINVAL, "device %d outside [0, %d)", device_ordinal, n);
+  sslic_ctx* c = new sslic_ctx;
+  c->device = device_ordinal;
+  if (hipSetDevice(device_ordinal) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_ints, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(SSLIC_EDEVICE, "cannot initialise device %d", device_ordinal);
+  }
+  *out = c;
+  return SSLIC_OK;
+}
+
+void sslic_destroy(sslic_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->host_ints) (void)hipHostFree(ctx->host_ints);
+  delete ctx;
+}
+
+int sslic_num_clusters(int ndim, const int64_t* dims, const int32_t* S, int64_t* K_out,
+                       int64_t* K_axis) {
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, 1, kU8, S, 1.0, 0);
+  if (rc) return rc;
+  if (K_out) *K_out = g.K;
+  if (K_axis)
+    for (int i = 0; i < ndim; ++i) K_axis[i] = g.Ka[i];
+  return SSLIC_OK;
+}
+
+int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, int channels,
+              sslic_dtype dtype, const int32_t* S, double m, int iterations,
+              const sslic_options* opt, int32_t* labels, double* centres, int64_t* counts,
+              int32_t* n_labels_out, int32_t* iters_done_out, sslic_stream_t stream) {
+  if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
+  if (!image || !labels || !centres) return fail(SSLIC_EINVAL, "image, labels and centres must be given");
+  if (iterations < 1) return fail(SSLIC_EINVAL, "iterations %d < 1", iterations);
+  sslic_options o{};
+  if (opt) o = *opt;
+  if (!(o.tol >= 0.0)) return fail(SSLIC_EINVAL, "tol must be >= 0");
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, 0);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  const bool cc = !o.no_connectivity;
+  Layout L = layout(g, iterations, cc);
+  if ((rc = ensure_ws(ctx, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Iter it = iter_view(ctx, L);
+  if (o.init_centres) {
+    if (o.init_centres != centres)
+      HIP_TRY(hipMemcpyAsync(centres, o.init_centres, (size_t)g.K * g.row * 8,
+                             hipMemcpyDeviceToDevice, s));
+  } else {
+    HIP_TRY(launch_seed(g, image, centres, s));
+  }
+  if ((rc = run_iterations(g, it, image, iterations, o.tol, labels, centres, counts, o.residuals, s)))
+    return rc;
+  int32_t* nl = nlab_slot(ctx, L);
+  if (cc) {
+    HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
+  } else {
+    HIP_TRY(launch_fill_i32(nl, (int32_t)g.K, 1, s));
+  }
+  if (o.n_labels_dev) HIP_TRY(hipMemcpyAsync(o.n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
+  if (o.iters_done_dev) HIP_TRY(hipMemcpyAsync(o.iters_done_dev, it.iters, 4, hipMemcpyDeviceToDevice, s));
+  return read_ints(ctx, s, nl, n_labels_out, it.iters, iters_done_out);
+}
+
+int sslic_run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic_options* opt,
+                    int32_t* n_labels_out, sslic_stream_t stream) {
+  if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
+  if (n < 0 || (n > 0 && !images)) return fail(SSLIC_EINVAL, "bad image list");
+  sslic_options o{};
+  if (opt) o = *opt;
+  for (int i = 0; i < n; ++i) {
+    const sslic_image_desc& d = images[i];
+    sslic_options oi{};
+    oi.tol = o.tol;
+    oi.no_connectivity = o.no_connectivity;
+    oi.residuals = d.residuals;
+    int rc = sslic_run(ctx, d.image, d.ndim, d.dims, d.channels, d.dtype, d.S, d.m, d.iterations, &oi,
+                       d.labels, d.centres, d.counts, n_labels_out ? n_labels_out + i : nullptr,
+                       nullptr, stream);
+    if (rc) return rc;
+  }
+  return SSLIC_OK;
+}
+
+int sslic_seed(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, int channels,
+               sslic_dtype dtype, const int32_t* S, double* centres_out, sslic_stream_t stream) {
+  if (!ctx || !image || !centres_out) return fail(SSLIC_EINVAL, "ctx, image and centres_out must be given");
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, 1.0, 0);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  HIP_TRY(launch_seed(g, image, centres_out, (hipStream_t)stream));
+  return SSLIC_OK;
+}
+
+int sslic_grid_labels(sslic_ctx* ctx, int ndim, const int64_t* dims, const int32_t* S, int32_t* labels,
+                      sslic_stream_t stream) {
+  if (!ctx || !labels) return fail(SSLIC_EINVAL, "ctx and labels must be given");
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, 1, kU8, S, 1.0, 0);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  HIP_TRY(launch_grid_labels(g, labels, (hipStream_t)stream));
+  return SSLIC_OK;
+}
+
+int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, int channels,
+                 sslic_dtype dtype, const int32_t* S, double m, const double* centres, int64_t K,
+                 int32_t* labels, sslic_stream_t stream) {
+  if (!ctx || !image || !centres || !labels) return fail(SSLIC_EINVAL, "missing pointer");
+  if (K < 1) return fail(SSLIC_EINVAL, "K = %lld < 1", (long long)K);
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, K);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  Layout L = layout(g, 1, false);
+  if ((rc = ensure_ws(ctx, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Iter it = iter_view(ctx, L);
+  HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
+  HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
+  HIP_TRY(launch_prep(g, centres, it, s));
+  HIP_TRY(launch_bins(g, it, s));
+  HIP_TRY(launch_assign(g, image, it, labels, 0, s));
+  return SSLIC_OK;
+}
+
+int sslic_update(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, int channels,
+                 sslic_dtype dtype, const int32_t* S, double m, const int32_t* labels, int64_t K,
+                 double* centres, int64_t* counts, double* residual, sslic_stream_t stream) {
+  if (!ctx || !image || !centres || !labels) return fail(SSLIC_EINVAL, "missing pointer");
+  if (K < 1) return fail(SSLIC_EINVAL, "K = %lld < 1", (long long)K);
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, K);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  Layout L = layout(g, 1, false);
+  if ((rc = ensure_ws(ctx, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Iter it = iter_view(ctx, L);
+  HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
+  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2, s));
+  HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
+  HIP_TRY(launch_update(g, image, labels, it, s));
+  HIP_TRY(launch_finalize(g, centres, counts, it, 0, 0, s));
+  HIP_TRY(launch_residual_finish(it, 0, -1.0, residual, s));
+  return SSLIC_OK;
+}
+
+int sslic_connectivity(sslic_ctx* ctx, int ndim, const int64_t* dims, const int32_t* S, int channels,
+                       const double* centres, int64_t K, int32_t* labels, int32_t* n_labels_out,
+                       int32_t* n_labels_dev, sslic_stream_t stream) {
+  if (!ctx || !centres || !labels) return fail(SSLIC_EINVAL, "missing pointer");
+  if (K < 1) return fail(SSLIC_EINVAL, "K = %lld < 1", (long long)K);
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, kU8, S, 1.0, K);
+  if (rc) return rc;
+  if ((rc = select_device(ctx))) return rc;
+  Layout L = layout(g, 1, true);
+  if ((rc = ensure_ws(ctx, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* nl = nlab_slot(ctx, L);
+  HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
+  if (n_labels_dev) HIP_TRY(hipMemcpyAsync(n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
+  return read_ints(ctx, s, nl, n_labels_out, nullptr, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// centres.hip -- seeding (Sec. 2.2 / 3.1 stage 1), the per-iteration centre
+// table and S-bin index, the mean update's final division and the residual
+// (Sec. 3.1 stage 2, Sec. 3.2).
+#include <cmath>
+
+#include "sslic_internal.h"
+
+namespace sslic {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int blocks_for(int64_t n, int per = kThreads) { return (int)((n + per - 1) / per); }
+
+template <typename T>
+__global__ void fill_kernel(T* p, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+hipError_t fill(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int nb = (int)std::min<int64_t>(blocks_for(n), 8192);
+  fill_kernel<T><<<nb, kThreads, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Seeding: grid seed, then the lowest squared Frobenius norm of the central
+// difference Jacobian among the in-image 3^n neighbours, visited in raster
+// order (offset along axis 0 fastest) and replaced only when strictly lower.
+
+template <typename T>
+__device__ __forceinline__ int64_t grad_int(const Geo& g, const T* img, const int* p, int nd) {
+  int64_t base = 0;
+  for (int i = 0; i < nd; ++i) base += p[i] * g.st[i];
+  int64_t acc = 0;
+  for (int c = 0; c < g.C; ++c) {
+    for (int i = 0; i < nd; ++i) {
+      int pp = min(p[i] + 1, g.n[i] - 1), pm = max(p[i] - 1, 0);
+      int64_t a = (int64_t)img[(base + (int64_t)(pp - p[i]) * g.st[i]) * g.C + c];
+      int64_t b = (int64_t)img[(base + (int64_t)(pm - p[i]) * g.st[i]) * g.C + c];
+      acc += (a - b) * (a - b);
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double grad_flt(const Geo& g, const float* img, const int* p, int nd) {
+#pragma clang fp contract(off)
+  int64_t base = 0;
+  for (int i = 0; i < nd; ++i) base += p[i] * g.st[i];
+  double acc = 0.0;
+  for (int c = 0; c < g.C; ++c) {
+    for (int i = 0; i < nd; ++i) {
+      int pp = min(p[i] + 1, g.n[i] - 1), pm = max(p[i] - 1, 0);
+      double a = (double)img[(base + (int64_t)(pp - p[i]) * g.st[i]) * g.C + c];
+      double b = (double)img[(base + (int64_t)(pm - p[i]) * g.st[i]) * g.C + c];
+      double d = a - b;
+      acc = acc + d * d;
+    }
+  }
+  return acc;
+}
+
+template <typename T, typename G>
+__device__ __forceinline__ G grad_any(const Geo& g, const T* img, const int* p, int nd) {
+  if constexpr (std::is_same<T, float>::value) return grad_flt(g, img, p, nd);
+  else return grad_int<T>(g, img, p, nd);
+}
+
+template <typename T>
+__global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict__ cen) {
+  using G = typename std::conditional<std::is_same<T, float>::value, double, int64_t>::type;
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  const int nd = g.nd;
+  int s[kMaxDim], q[kMaxDim], best[kMaxDim];
+  int64_t r = k;
+  for (int i = 0; i < nd; ++i) {
+    int64_t j = r % g.Ka[i];
+    r /= g.Ka[i];
+    s[i] = (int)(((2 * j + 1) * (int64_t)g.n[i]) / (2 * (int64_t)g.Ka[i]));
+    best[i] = s[i];
+  }
+  G gb = grad_any<T, G>(g, img, s, nd);
+  int n3 = 1;
+  for (int i = 0; i < nd; ++i) n3 *= 3;
+  for (int o = 0; o < n3; ++o) {
+    int oo = o;
+    bool inside = true;
+    for (int i = 0; i < nd; ++i) {
+      q[i] = s[i] + (oo % 3) - 1;
+      oo /= 3;
+      inside = inside && q[i] >= 0 && q[i] < g.n[i];
+    }
+    if (!inside) continue;
+    G v = grad_any<T, G>(g, img, q, nd);
+    if (v < gb) {
+      gb = v;
+      for (int i = 0; i < nd; ++i) best[i] = q[i];
+    }
+  }
+  int64_t bl = 0;
+  for (int i = 0; i < nd; ++i) bl += best[i] * g.st[i];
+  double* row = cen + k * g.row;
+  for (int c = 0; c < g.C; ++c) row[c] = (double)img[bl * g.C + c];
+  for (int i = 0; i < g.nd_out; ++i) row[g.C + i] = (double)best[i];
+}
+
+__global__ void grid_labels_kernel(Geo g, int32_t* __restrict__ labels) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = v, k = 0, kst = 1;
+    for (int i = 0; i < g.nd; ++i) {
+      int64_t x = r % g.n[i];
+      r /= g.n[i];
+      k += (x * g.Ka[i] / g.n[i]) * kst;
+      kst *= g.Ka[i];
+    }
+    labels[v] = (int32_t)k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Centre table and bins.  The window of centre k on axis i is the integer
+// range [ceil(c - S), floor(c + S)], computed in FP64 exactly as the closed
+// condition |x - c| <= S reads.  Bin b = floor(lo / S) + 1 (clamped) is within
+// one bin of the bin of every voxel the window holds, so a voxel finds every
+// centre that covers it among the 3^n bins around its own.
+
+__device__ __forceinline__ int floordiv(int a, int b) {
+  int q = a / b;
+  return (q * b > a) ? q - 1 : q;
+}
+
+__device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_t k, const Iter& it) {
+  float* rec = it.ctab + k * g.rs;
+  int32_t* irec = reinterpret_cast<int32_t*>(rec);
+  for (int c = 0; c < g.C; ++c) rec[c] = (float)row[c];
+  int64_t bin = 0;
+  for (int i = 0; i < g.nd; ++i) {
+    double ci = i < g.nd_out ? row[g.C + i] : 0.0;
+    rec[g.C + i] = (float)ci;
+    int lo, hi;
+    if (isfinite(ci)) {
+      double l = ceil(ci - (double)g.S[i]);
+      double h = floor(ci + (double)g.S[i]);
+      l = fmin(fmax(l, -1073741824.0), 1073741824.0);
+      h = fmin(fmax(h, -1073741824.0), 1073741824.0);
+      lo = (int)l;
+      hi = (int)h;
+    } else {
+      lo = 1073741824;
+      hi = -1073741824;
+    }
+    irec[g.C + g.nd + i] = lo;
+    irec[g.C + 2 * g.nd + i] = hi;
+    int b = floordiv(lo, g.S[i]) + 1;
+    b = min(max(b, 0), g.nb[i] - 1);
+    bin += b * g.bst[i];
+  }
+  it.bin_of[k] = (int32_t)bin;
+  atomicAdd(&it.bin_cnt[bin], 1);
+}
+
+__global__ void prep_kernel(Geo g, const double* __restrict__ cen, Iter it) {
+  if (*it.done) return;
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  prep_one(g, cen + k * g.row, k, it);
+}
+
+// Exclusive scan of bin counts in blocks of 4096 (16 per thread), then a
+// single-block scan of block totals, then the offsets.  The counts are reset
+// to zero on the way so they can serve as scatter cursors.
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = kThreads * kScanPer;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  // sh: kThreads ints.  Hillis-Steele over the block.
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  int incl = sh[t];
+  *total = sh[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void scan_local_kernel(int32_t* __restrict__ cnt, int32_t* __restrict__ out,
+                                  int32_t* __restrict__ part, int64_t n, const int32_t* done) {
+  if (*done) return;
+  __shared__ int sh[kThreads];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int sum = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    int64_t i = base + j;
+    v[j] = i < n ? cnt[i] : 0;
+    if (i < n) cnt[i] = 0;
+    sum += v[j];
+  }
+  int total;
+  int off = block_exclusive_scan(sum, sh, &total);
+  for (int j = 0; j < kScanPer; ++j) {
+    int64_t i = base + j;
+    if (i < n) out[i] = off;
+    off += v[j];
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void scan_parts_kernel(int32_t* __restrict__ part, int nparts, int32_t* __restrict__ out_last,
+                                  const int32_t* done) {
+  if (*done) return;
+  __shared__ int sh[kThreads];
+  int carry = 0;
+  for (int b0 = 0; b0 < nparts; b0 += kThreads) {
+    int i = b0 + threadIdx.x;
+    int v = i < nparts ? part[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, sh, &total);
+    if (i < nparts) part[i] = ex + carry;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out_last = carry;
+}
+
+__global__ void scan_add_kernel(int32_t* __restrict__ out, const int32_t* __restrict__ part, int64_t n,
+                                const int32_t* done) {
+  if (*done) return;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += part[i / kScanBlock];
+}
+
+__global__ void scatter_kernel(Geo g, Iter it) {
+  if (*it.done) return;
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  int b = it.bin_of[k];
+  int pos = it.bin_start[b] + atomicAdd(&it.bin_cnt[b], 1);
+  it.bin_items[pos] = (int32_t)k;
+}
+
+// Order each bin's items by cluster index (bins hold a handful of centres)
+// and reset the cursors for the next use.
+__global__ void binsort_kernel(Geo g, Iter it) {
+  if (*it.done) return;
+  int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= g.nbins) return;
+  int a = it.bin_start[b], e = it.bin_start[b + 1];
+  for (int i = a + 1; i < e; ++i) {
+    int v = it.bin_items[i];
+    int j = i - 1;
+    while (j >= a && it.bin_items[j] > v) {
+      it.bin_items[j + 1] = it.bin_items[j];
+      --j;
+    }
+    it.bin_items[j + 1] = v;
+  }
+  it.bin_cnt[b] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Update, final step: sums / count in FP64 (correctly rounded, as the oracle),
+// the residual term of the cluster, counts out, accumulators reset, and the
+// table and bin of the new centre for the next assignment.
+
+__device__ __forceinline__ double warp_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ void finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts,
+                                Iter it, int t, int prep_next) {
+  if (*it.done) return;
+  __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double e_sum = 0.0, e_cnt = 0.0;
+  if (k < g.K) {
+    uint64_t* a = it.acc + k * g.F;
+    uint64_t n = a[0];
+    double* row = cen + k * g.row;
+    if (n > 0) {
+      double dn = (double)n;
+      double e = 0.0;
+      for (int c = 0; c < g.C; ++c) {
+        uint64_t raw = a[1 + g.nd + c];
+        double nv = g.dtype == kF32 ? __longlong_as_double((long long)raw) / dn : (double)raw / dn;
+        double d = nv - row[c];
+        e = e + d * d;
+        row[c] = nv;
+      }
+      for (int i = 0; i < g.nd_out; ++i) {
+        double nv = (double)a[1 + i] / dn;
+        double d = nv - row[g.C + i];
+        e = e + g.wd[i] * (d * d);
+        row[g.C + i] = nv;
+      }
+      e_sum = sqrt(e);
+      e_cnt = 1.0;
+    }
+    if (counts) counts[k] = (int64_t)n;
+    for (int f = 0; f < g.F; ++f) a[f] = 0;
+    if (prep_next) prep_one(g, row, k, it);
+  }
+  e_sum = warp_sum(e_sum);
+  e_cnt = warp_sum(e_cnt);
+  int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+  if (ln == 0) {
+    sh_e[wv] = e_sum;
+    sh_n[wv] = e_cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < kThreads / 64; ++i) {
+      s += sh_e[i];
+      c += sh_n[i];
+    }
+    if (c > 0.0) {
+      atomicAdd(&it.res_acc[2 * t], s);
+      atomicAdd(&it.res_acc[2 * t + 1], c);
+    }
+  }
+}
+
+__global__ void residual_finish_kernel(Iter it, int t, double tol, double* residuals) {
+  if (*it.done) return;
+  double s = it.res_acc[2 * t], c = it.res_acc[2 * t + 1];
+  double e = c > 0.0 ? s / c : 0.0;
+  if (residuals) residuals[t] = e;
+  *it.iters = t + 1;
+  if (e < tol) *it.done = 1;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
+
+hipError_t launch_seed(const Geo& g, const void* img, double* cen, hipStream_t s) {
+  int nb = blocks_for(g.K);
+  switch (g.dtype) {
+    case kU8: seed_kernel<uint8_t><<<nb, kThreads, 0, s>>>(g, (const uint8_t*)img, cen); break;
+    case kU16: seed_kernel<uint16_t><<<nb, kThreads, 0, s>>>(g, (const uint16_t*)img, cen); break;
+    default: seed_kernel<float><<<nb, kThreads, 0, s>>>(g, (const float*)img, cen); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_labels(const Geo& g, int32_t* labels, hipStream_t s) {
+  int nb = (int)std::min<int64_t>(blocks_for(g.N), 65536);
+  grid_labels_kernel<<<nb, kThreads, 0, s>>>(g, labels);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const Geo& g, const double* cen, const Iter& it, hipStream_t s) {
+  prep_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s) {
+  int nparts = (int)((g.nbins + kScanBlock - 1) / kScanBlock);
+  scan_local_kernel<<<nparts, kThreads, 0, s>>>(it.bin_cnt, it.bin_start, it.scan_part, g.nbins, it.done);
+  scan_parts_kernel<<<1, kThreads, 0, s>>>(it.scan_part, nparts, it.bin_start + g.nbins, it.done);
+  scan_add_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(it.bin_start, it.scan_part, g.nbins, it.done);
+  scatter_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, it);
+  binsort_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(g, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Iter& it, int t,
+                           int prep_next, hipStream_t s) {
+  finalize_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, counts, it, t, prep_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_finish(const Iter& it, int t, double tol, double* residuals, hipStream_t s) {
+  residual_finish_kernel<<<1, 1, 0, s>>>(it, t, tol, residuals);
+  return hipGetLastError();
+}
+
+}  // namespace sslic

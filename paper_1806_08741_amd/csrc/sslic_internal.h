@@ -1,0 +1,102 @@
+// sslic_internal.h -- geometry, workspace views and kernel launchers shared by
+// the HIP sources of libsslic.so.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sslic {
+
+constexpr int kMaxDim = 4;
+constexpr int kMaxChan = 8;
+
+enum Dtype { kU8 = 0, kU16 = 1, kF32 = 2 };
+
+// Geometry of one image as the kernels see it.  Images with one axis are
+// handled as two-dimensional with a second axis of size 1 (grid step 1),
+// which leaves every result unchanged; `nd_out` is the caller's axis count
+// and the number of coordinate columns of its centre table.
+struct Geo {
+  int nd;            // axes the kernels iterate (2..4)
+  int nd_out;        // caller's axes (1..4)
+  int C;             // channels
+  int dtype;         // Dtype
+  int n[kMaxDim];    // size per axis (1 beyond nd)
+  int64_t st[kMaxDim];  // voxel stride per axis
+  int64_t N;         // voxels
+  int S[kMaxDim];    // grid step per axis (index units)
+  int Ka[kMaxDim];   // clusters per axis
+  int64_t K;         // clusters
+  int nb[kMaxDim];   // S-bins per axis = ceil(n / S)
+  int64_t bst[kMaxDim];  // bin stride per axis
+  int64_t nbins;
+  float w[kMaxDim];  // (m / S_i)^2 in FP32 (assignment distance)
+  double wd[kMaxDim];  // (m / S_i)^2 in FP64 (residual)
+  int rs;            // words per record of the assignment centre table
+  int64_t prodS;     // prod S_i (connectivity threshold 4 size > prodS)
+  int F;             // 8-byte accumulator words per cluster = 1 + nd + C
+  int row;           // doubles per row of the caller's centre table = C + nd_out
+};
+
+// Record k of the assignment centre table (FP32 words, stride g.rs):
+//   [0, C)            channel means mu_c
+//   [C, C+nd)         coordinates c_i
+//   [C+nd, C+2nd)     int32 lo_i = ceil(c_i - S_i)   (FP64, clamped)
+//   [C+2nd, C+3nd)    int32 hi_i = floor(c_i + S_i)
+// so that x is inside the closed window of k iff lo_i <= x_i <= hi_i.
+__host__ __device__ inline int rec_words(int C, int nd) { return (C + 3 * nd + 3) & ~3; }
+
+// Device buffers used by one iteration loop.
+struct Iter {
+  float* ctab;        // [K][rs]
+  int32_t* bin_of;    // [K]
+  int32_t* bin_cnt;   // [nbins]   counts, then cursors; zero between uses
+  int32_t* bin_start; // [nbins + 1]
+  int32_t* bin_items; // [K]
+  int32_t* scan_part; // [ceil(nbins / 4096) + 1]
+  uint64_t* acc;      // [K][F]    zero between uses
+  double* res_acc;    // [2 * iterations]  (sum, count) per iteration
+  int32_t* done;      // converged flag: kernels return early when set
+  int32_t* iters;     // iterations run
+};
+
+// ---- launchers (each returns the hipError_t of its launches) -------------
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+hipError_t launch_seed(const Geo& g, const void* img, double* cen, hipStream_t s);
+hipError_t launch_grid_labels(const Geo& g, int32_t* labels, hipStream_t s);
+
+// f64 centres -> assignment table + bin of every cluster + bin counts
+hipError_t launch_prep(const Geo& g, const double* cen, const Iter& it, hipStream_t s);
+// bin counts -> CSR (bin_start, bin_items sorted by cluster index)
+hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s);
+
+hipError_t launch_assign(const Geo& g, const void* img, const Iter& it, int32_t* labels,
+                         int first, hipStream_t s);
+hipError_t launch_update(const Geo& g, const void* img, const int32_t* labels,
+                         const Iter& it, hipStream_t s);
+// accumulators -> new centres, counts, residual partials; then prep for the
+// next iteration (table, bins) when `prep_next`
+hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Iter& it,
+                           int t, int prep_next, hipStream_t s);
+// residual of iteration t -> residuals[t] (if non-null), done flag, iteration count
+hipError_t launch_residual_finish(const Iter& it, int t, double tol, double* residuals,
+                                  hipStream_t s);
+
+// connectivity scratch
+struct CCBuf {
+  int32_t* parent;    // [N]
+  int32_t* size;      // [N]
+  uint8_t* final_;    // [N]
+  int32_t* newlab;    // [N] label of each component root
+  int32_t* part;      // [ceil(N / 4096) + 1] block counts / offsets
+  int32_t* total;     // [1] number of new labels
+};
+hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
+                               const CCBuf& b, int32_t* n_labels_dev, hipStream_t s);
+
+}  // namespace sslic

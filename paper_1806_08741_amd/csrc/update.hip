@@ -1,0 +1,176 @@
+// update.hip -- the map step of the update (Sec. 3.1 stage 2): per-cluster
+// sums of [1, x, I(x)] over the voxels carrying each label.
+//
+// A workgroup owns a tile of 64 columns (axis 0) by 64 rows (the other axes
+// flattened).  Each lane walks one column of 16 rows and keeps a running sum
+// for the current label (labels are spatially coherent, so runs are long);
+// when the label changes the run is added into a small LDS hash table keyed
+// by label.  At the end the table is added into the global per-cluster
+// accumulators with one atomic per field and label present in the tile.
+// Integer images and all coordinates are summed as 64-bit integers (exact);
+// float32 channels in FP64.
+#include "sslic_internal.h"
+
+namespace sslic {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kCols = 64;
+constexpr int kRowsPerWave = 16;
+constexpr int kRows = kRowsPerWave * (kThreads / 64);
+constexpr int kHash = 256;
+constexpr int kMaxF = 1 + kMaxDim + kMaxChan;
+
+template <bool FLT>
+struct ChanSum {
+  using type = uint64_t;
+};
+template <>
+struct ChanSum<true> {
+  using type = double;
+};
+
+__device__ __forceinline__ void add_global(const Geo& g, uint64_t* acc, int64_t key, int f, uint64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(acc + key * g.F + f), (unsigned long long)v);
+}
+__device__ __forceinline__ void add_global_f(const Geo& g, uint64_t* acc, int64_t key, int f, double v) {
+  atomicAdd(reinterpret_cast<double*>(acc + key * g.F + f), v);
+}
+
+template <typename T, int ND, int CC>
+__global__ void __launch_bounds__(kThreads)
+update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labels, Iter it) {
+  if (*it.done) return;
+  constexpr bool FLT = std::is_same<T, float>::value;
+  using CS = typename ChanSum<FLT>::type;
+  const int C = CC > 0 ? CC : g.C;
+  const int F = g.F;
+  __shared__ int keys[kHash];
+  __shared__ uint64_t vals[kHash * kMaxF];
+
+  for (int i = threadIdx.x; i < kHash; i += kThreads) keys[i] = -1;
+  for (int i = threadIdx.x; i < kHash * F; i += kThreads) vals[i] = 0;
+  __syncthreads();
+
+  const int n0 = g.n[0];
+  const int64_t nrows = g.N / n0;
+  const int tiles_x = (n0 + kCols - 1) / kCols;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t tile = blockIdx.x;
+  const int x = (int)(tile % tiles_x) * kCols + lane;
+  const int64_t r0 = (tile / tiles_x) * kRows + (int64_t)wave * kRowsPerWave;
+
+  int cur = -1;
+  uint32_t cnt = 0;
+  uint64_t sc[ND];
+  CS sch[CC > 0 ? CC : kMaxChan];
+  for (int i = 0; i < ND; ++i) sc[i] = 0;
+  for (int c = 0; c < C; ++c) sch[c] = 0;
+
+  auto flush = [&]() {
+    if (cur < 0 || cur >= g.K || cnt == 0) return;
+    uint32_t h = ((uint32_t)cur * 2654435761u) >> (32 - 8);  // kHash = 256
+    int slot = -1;
+    for (int p = 0; p < kHash; ++p) {
+      int old = atomicCAS(&keys[h], -1, cur);
+      if (old == -1 || old == cur) {
+        slot = (int)h;
+        break;
+      }
+      h = (h + 1) & (kHash - 1);
+    }
+    if (slot >= 0) {
+      uint64_t* vv = vals + slot * F;
+      atomicAdd(reinterpret_cast<unsigned long long*>(vv), (unsigned long long)cnt);
+      for (int i = 0; i < ND; ++i) atomicAdd(reinterpret_cast<unsigned long long*>(vv + 1 + i), (unsigned long long)sc[i]);
+      for (int c = 0; c < C; ++c) {
+        if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(vv + 1 + ND + c), (double)sch[c]);
+        else atomicAdd(reinterpret_cast<unsigned long long*>(vv + 1 + ND + c), (unsigned long long)sch[c]);
+      }
+    } else {  // table full: straight to the global accumulators
+      add_global(g, it.acc, cur, 0, cnt);
+      for (int i = 0; i < ND; ++i) add_global(g, it.acc, cur, 1 + i, sc[i]);
+      for (int c = 0; c < C; ++c) {
+        if constexpr (FLT) add_global_f(g, it.acc, cur, 1 + ND + c, (double)sch[c]);
+        else add_global(g, it.acc, cur, 1 + ND + c, (uint64_t)sch[c]);
+      }
+    }
+  };
+
+  if (x < n0) {
+    for (int j = 0; j < kRowsPerWave; ++j) {
+      int64_t r = r0 + j;
+      if (r >= nrows) break;
+      int64_t v = r * n0 + x;
+      int l = labels[v];
+      if (l != cur) {
+        flush();
+        cur = l;
+        cnt = 0;
+        for (int i = 0; i < ND; ++i) sc[i] = 0;
+        for (int c = 0; c < C; ++c) sch[c] = 0;
+      }
+      ++cnt;
+      sc[0] += (uint64_t)x;
+      int64_t rr = r;
+      for (int i = 1; i < ND; ++i) {
+        sc[i] += (uint64_t)(rr % g.n[i]);
+        rr /= g.n[i];
+      }
+      for (int c = 0; c < C; ++c) sch[c] += (CS)img[v * C + c];
+    }
+    flush();
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < kHash; s += kThreads) {
+    int key = keys[s];
+    if (key < 0) continue;
+    const uint64_t* vv = vals + s * F;
+    add_global(g, it.acc, key, 0, vv[0]);
+    for (int i = 0; i < ND; ++i) add_global(g, it.acc, key, 1 + i, vv[1 + i]);
+    for (int c = 0; c < C; ++c) {
+      if constexpr (FLT) add_global_f(g, it.acc, key, 1 + ND + c, __longlong_as_double((long long)vv[1 + ND + c]));
+      else add_global(g, it.acc, key, 1 + ND + c, vv[1 + ND + c]);
+    }
+  }
+}
+
+template <typename T, int ND>
+hipError_t dispatch_c(const Geo& g, const void* img, const int32_t* labels, const Iter& it,
+                      hipStream_t s) {
+  const int64_t tiles_x = (g.n[0] + kCols - 1) / kCols;
+  const int64_t nrows = g.N / g.n[0];
+  const int64_t nb = tiles_x * ((nrows + kRows - 1) / kRows);
+  const T* p = (const T*)img;
+  switch (g.C) {
+    case 1: update_kernel<T, ND, 1><<<(unsigned)nb, kThreads, 0, s>>>(g, p, labels, it); break;
+    case 3: update_kernel<T, ND, 3><<<(unsigned)nb, kThreads, 0, s>>>(g, p, labels, it); break;
+    case 4: update_kernel<T, ND, 4><<<(unsigned)nb, kThreads, 0, s>>>(g, p, labels, it); break;
+    default: update_kernel<T, ND, 0><<<(unsigned)nb, kThreads, 0, s>>>(g, p, labels, it); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_nd(const Geo& g, const void* img, const int32_t* labels, const Iter& it,
+                       hipStream_t s) {
+  switch (g.nd) {
+    case 2: return dispatch_c<T, 2>(g, img, labels, it, s);
+    case 3: return dispatch_c<T, 3>(g, img, labels, it, s);
+    default: return dispatch_c<T, 4>(g, img, labels, it, s);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_update(const Geo& g, const void* img, const int32_t* labels, const Iter& it,
+                         hipStream_t s) {
+  switch (g.dtype) {
+    case kU8: return dispatch_nd<uint8_t>(g, img, labels, it, s);
+    case kU16: return dispatch_nd<uint16_t>(g, img, labels, it, s);
+    default: return dispatch_nd<float>(g, img, labels, it, s);
+  }
+}
+
+}  // namespace sslic

@@ -1,0 +1,304 @@
+"""Thin ctypes binding of libsslic.so (include/sslic.h, include/sslic_steps.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the computation runs in the library's HIP kernels.
+There is no CPU fallback -- a missing library or a missing GPU raises.
+
+Images are torch tensors of shape ``(*reversed(dims), C)`` (C order, so the
+channel is fastest, then axis 0), dtype uint8, uint16 or float32, on a CUDA
+(HIP) device.  Labels come back as flat int32 tensors in linear order (axis 0
+fastest) and centres as float64 ``(K, C + ndim)`` tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsslic.so")
+
+_DT = {torch.uint8: 0, torch.uint16: 1, torch.float32: 2}
+
+P = ctypes.c_void_p
+I = ctypes.c_int
+I64 = ctypes.c_int64
+D = ctypes.c_double
+
+
+class SslicError(RuntimeError):
+    pass
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("tol", D), ("no_connectivity", I), ("init_centres", P), ("residuals", P),
+                ("iters_done_dev", P), ("n_labels_dev", P)]
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("image", P), ("ndim", I), ("dims", I64 * 4), ("channels", I), ("dtype", I),
+                ("S", ctypes.c_int32 * 4), ("m", D), ("iterations", I), ("labels", P),
+                ("centres", P), ("counts", P), ("residuals", P)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libsslic.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise SslicError(f"{LIB_PATH} is missing: build it first "
+                                 "(python -c 'import __graft_entry__ as g; g.build()')")
+            L = ctypes.CDLL(LIB_PATH)
+            L.sslic_last_error.restype = ctypes.c_char_p
+            L.sslic_create.argtypes = [ctypes.POINTER(P), I]
+            L.sslic_destroy.argtypes = [P]
+            L.sslic_destroy.restype = None
+            L.sslic_num_clusters.argtypes = [I, P, P, P, P]
+            L.sslic_run.argtypes = [P, P, I, P, I, I, P, D, I, ctypes.POINTER(_Options), P, P, P,
+                                    P, P, P]
+            L.sslic_run_batch.argtypes = [P, ctypes.POINTER(ImageDesc), I,
+                                          ctypes.POINTER(_Options), P, P]
+            L.sslic_seed.argtypes = [P, P, I, P, I, I, P, P, P]
+            L.sslic_grid_labels.argtypes = [P, I, P, P, P, P]
+            L.sslic_assign.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P]
+            L.sslic_update.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P, P, P]
+            L.sslic_connectivity.argtypes = [P, I, P, P, I, P, I64, P, P, P, P]
+            for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_batch",
+                         "sslic_seed", "sslic_grid_labels", "sslic_assign", "sslic_update",
+                         "sslic_connectivity"):
+                getattr(L, name).restype = I
+            _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().sslic_last_error().decode(errors="replace")
+        raise SslicError(f"libsslic error {rc}: {msg}")
+
+
+def _i64(vals):
+    return (I64 * len(vals))(*[int(v) for v in vals])
+
+
+def _i32(vals):
+    return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+def _stream(dev: torch.device):
+    return P(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else P(t.data_ptr())
+
+
+def num_clusters(dims: Sequence[int], S: Sequence[int]) -> int:
+    k = I64(0)
+    _check(lib().sslic_num_clusters(len(dims), _i64(dims), _i32(S), ctypes.byref(k), None))
+    return int(k.value)
+
+
+def _geom(img: torch.Tensor):
+    if not img.is_cuda:
+        raise SslicError("the image must be on a GPU; there is no CPU path")
+    if img.dtype not in _DT:
+        raise SslicError(f"unsupported dtype {img.dtype}")
+    if not img.is_contiguous():
+        raise SslicError("the image must be contiguous")
+    nd = img.dim() - 1
+    dims = list(img.shape[:nd])[::-1]
+    return nd, dims, int(img.shape[-1]), _DT[img.dtype]
+
+
+class Context:
+    """A libsslic context (owns the device workspace) bound to one device."""
+
+    def __init__(self, device: int | torch.device = 0):
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if dev.type != "cuda":
+            raise SslicError("libsslic needs a GPU device")
+        self.device = dev
+        h = P()
+        _check(lib().sslic_create(ctypes.byref(h), dev.index or 0))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sslic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- whole filter -------------------------------------------------------
+    def run(self, img: torch.Tensor, S: Sequence[int], m: float, iterations: int, *,
+            tol: float = 0.0, connectivity: bool = True,
+            init_centres: Optional[torch.Tensor] = None, residuals: bool = False,
+            out: Optional[dict] = None, sync: bool = True) -> dict:
+        """Run SSLIC on one image.  ``out`` may hold preallocated ``labels``,
+        ``centres``, ``counts`` tensors.  With ``sync`` the label count and the
+        iterations run are read back (the call then waits for the stream)."""
+        nd, dims, C, dt = _geom(img)
+        K = num_clusters(dims, S)
+        N = int(img.numel() // C)
+        dev = img.device
+        out = dict(out or {})
+        labels = out.get("labels")
+        if labels is None:
+            labels = torch.empty(N, dtype=torch.int32, device=dev)
+        centres = out.get("centres")
+        if centres is None:
+            centres = torch.empty((K, C + nd), dtype=torch.float64, device=dev)
+        counts = out.get("counts")
+        if counts is None:
+            counts = torch.empty(K, dtype=torch.int64, device=dev)
+        res = torch.zeros(iterations, dtype=torch.float64, device=dev) if residuals else None
+        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None)
+        if init_centres is not None:
+            ic = init_centres.to(device=dev, dtype=torch.float64).contiguous()
+            o.init_centres = ic.data_ptr()
+        if res is not None:
+            o.residuals = res.data_ptr()
+        nl = ctypes.c_int32(0)
+        it = ctypes.c_int32(0)
+        _check(lib().sslic_run(self._h, _ptr(img), nd, _i64(dims), C, dt, _i32(S), float(m),
+                               int(iterations), ctypes.byref(o), _ptr(labels), _ptr(centres),
+                               _ptr(counts), ctypes.byref(nl) if sync else None,
+                               ctypes.byref(it) if sync else None, _stream(dev)))
+        r = {"labels": labels, "centres": centres, "counts": counts}
+        if res is not None:
+            r["residuals"] = res
+        if sync:
+            r["n_labels"] = int(nl.value)
+            r["iterations"] = int(it.value)
+            if res is not None:
+                r["residuals"] = res[: r["iterations"]]
+        return r
+
+    def run_batch(self, items: list, *, tol: float = 0.0, connectivity: bool = False,
+                  sync: bool = True) -> list:
+        """Run many images in one batched call.  ``items`` holds dicts with
+        ``image``, ``S``, ``m``, ``iterations`` and optional preallocated
+        ``labels``/``centres``/``counts``/``residuals``."""
+        n = len(items)
+        descs = (ImageDesc * max(n, 1))()
+        outs = []
+        for i, itm in enumerate(items):
+            img = itm["image"]
+            nd, dims, C, dt = _geom(img)
+            S = list(itm["S"])
+            K = num_clusters(dims, S)
+            N = int(img.numel() // C)
+            dev = img.device
+            lab = itm.get("labels")
+            if lab is None:
+                lab = torch.empty(N, dtype=torch.int32, device=dev)
+            cen = itm.get("centres")
+            if cen is None:
+                cen = torch.empty((K, C + nd), dtype=torch.float64, device=dev)
+            cnt = itm.get("counts")
+            if cnt is None:
+                cnt = torch.empty(K, dtype=torch.int64, device=dev)
+            res = itm.get("residuals")
+            if res is None and itm.get("want_residuals"):
+                res = torch.zeros(int(itm["iterations"]), dtype=torch.float64, device=dev)
+            d = descs[i]
+            d.image = img.data_ptr()
+            d.ndim = nd
+            for a in range(4):
+                d.dims[a] = int(dims[a]) if a < nd else 1
+                d.S[a] = int(S[a]) if a < nd else 1
+            d.channels = C
+            d.dtype = dt
+            d.m = float(itm["m"])
+            d.iterations = int(itm["iterations"])
+            d.labels = lab.data_ptr()
+            d.centres = cen.data_ptr()
+            d.counts = cnt.data_ptr()
+            d.residuals = res.data_ptr() if res is not None else None
+            outs.append({"labels": lab, "centres": cen, "counts": cnt, "residuals": res})
+        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None)
+        nl = (ctypes.c_int32 * max(n, 1))()
+        dev = items[0]["image"].device if n else self.device
+        _check(lib().sslic_run_batch(self._h, descs, n, ctypes.byref(o), nl if sync else None,
+                                     _stream(dev)))
+        if sync:
+            for i in range(n):
+                outs[i]["n_labels"] = int(nl[i])
+        return outs
+
+    # -- single steps -------------------------------------------------------
+    def seed(self, img: torch.Tensor, S: Sequence[int]) -> torch.Tensor:
+        nd, dims, C, dt = _geom(img)
+        K = num_clusters(dims, S)
+        cen = torch.empty((K, C + nd), dtype=torch.float64, device=img.device)
+        _check(lib().sslic_seed(self._h, _ptr(img), nd, _i64(dims), C, dt, _i32(S), _ptr(cen),
+                                _stream(img.device)))
+        return cen
+
+    def grid_labels(self, dims: Sequence[int], S: Sequence[int]) -> torch.Tensor:
+        N = 1
+        for d in dims:
+            N *= int(d)
+        lab = torch.empty(N, dtype=torch.int32, device=self.device)
+        _check(lib().sslic_grid_labels(self._h, len(dims), _i64(dims), _i32(S), _ptr(lab),
+                                       _stream(self.device)))
+        return lab
+
+    def assign(self, img: torch.Tensor, S, m, centres: torch.Tensor, labels: torch.Tensor):
+        """One assignment step in place on ``labels`` (kept where no window reaches)."""
+        nd, dims, C, dt = _geom(img)
+        centres = centres.to(device=img.device, dtype=torch.float64).contiguous()
+        assert labels.dtype == torch.int32 and labels.is_contiguous() and labels.is_cuda
+        _check(lib().sslic_assign(self._h, _ptr(img), nd, _i64(dims), C, dt, _i32(S), float(m),
+                                  _ptr(centres), centres.shape[0], _ptr(labels),
+                                  _stream(img.device)))
+        return labels
+
+    def update(self, img: torch.Tensor, S, m, labels: torch.Tensor, centres: torch.Tensor):
+        """One update step: returns (new centres, counts, residual tensor[1])."""
+        nd, dims, C, dt = _geom(img)
+        cen = centres.to(device=img.device, dtype=torch.float64).clone().contiguous()
+        K = cen.shape[0]
+        counts = torch.empty(K, dtype=torch.int64, device=img.device)
+        res = torch.zeros(1, dtype=torch.float64, device=img.device)
+        _check(lib().sslic_update(self._h, _ptr(img), nd, _i64(dims), C, dt, _i32(S), float(m),
+                                  _ptr(labels), K, _ptr(cen), _ptr(counts), _ptr(res),
+                                  _stream(img.device)))
+        return cen, counts, res
+
+    def connectivity(self, dims, S, centres: torch.Tensor, C: int, labels: torch.Tensor) -> int:
+        """Connectivity enforcement in place on ``labels``; returns n_labels."""
+        centres = centres.to(device=labels.device, dtype=torch.float64).contiguous()
+        nl = ctypes.c_int32(0)
+        _check(lib().sslic_connectivity(self._h, len(dims), _i64(dims), _i32(S), int(C),
+                                        _ptr(centres), centres.shape[0], _ptr(labels),
+                                        ctypes.byref(nl), None, _stream(labels.device)))
+        return int(nl.value)
+
+
+_default: dict = {}
+
+
+def context(device: int = 0) -> Context:
+    """A shared context per device."""
+    c = _default.get(device)
+    if c is None:
+        c = _default[device] = Context(device)
+    return c
+
+
+def run(img: torch.Tensor, S, m, iterations, **kw) -> dict:
+    return context(img.device.index or 0).run(img, S, m, iterations, **kw)

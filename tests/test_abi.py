@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the public headers declare, and rejects invalid arguments
+before touching a device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1806_08741_amd import sslic
+    if not os.path.exists(sslic.LIB_PATH):
+        from paper_1806_08741_amd import build
+        build.build()
+    return sslic.lib()
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:int|void|const char\s*\*)\s+(sslic_\w+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_headers_declare_the_entry_points():
+    names = declared_functions()
+    for n in ("sslic_create", "sslic_run", "sslic_destroy", "sslic_run_batch", "sslic_seed",
+              "sslic_assign", "sslic_update", "sslic_connectivity", "sslic_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), f"{n} declared but not exported"
+
+
+def test_num_clusters_host_only(lib):
+    from paper_1806_08741_amd import sslic
+    assert sslic.num_clusters([256, 256], [16, 16]) == 256
+    assert sslic.num_clusters([16384, 16384], [16, 16]) == 1 << 20
+    assert sslic.num_clusters([1024] * 3, [8] * 3) == 1 << 21
+    assert sslic.num_clusters([100], [7]) == 14
+    import oracle
+    for dims, S in [((37, 23), (8, 5)), ((16, 9, 7), (4, 4, 3)), ((5, 4, 3, 2), (2, 2, 2, 2))]:
+        assert sslic.num_clusters(dims, S) == oracle.num_clusters(dims, S)[0]
+
+
+@pytest.mark.parametrize("ndim,dims,S,msg", [
+    (0, [4], [1], "ndim"), (5, [2] * 5, [1] * 5, "ndim"), (2, [0, 4], [1, 1], "dims"),
+    (2, [4, 4], [0, 1], "S"), (2, [1 << 16, 1 << 16], [1, 1], "2^31")])
+def test_num_clusters_rejects(lib, ndim, dims, S, msg):
+    from paper_1806_08741_amd import sslic
+    k = ctypes.c_int64(0)
+    rc = lib.sslic_num_clusters(ndim, sslic._i64(dims), sslic._i32(S), ctypes.byref(k), None)
+    assert rc == -1
+    assert msg in lib.sslic_last_error().decode()
+
+
+def test_run_validates_before_any_device_work(lib):
+    """Invalid requests are refused with SSLIC_EINVAL before the context or
+    any device pointer is used (a dummy non-null context suffices)."""
+    from paper_1806_08741_amd import sslic
+    dummy = ctypes.create_string_buffer(64)
+    ctxp = ctypes.cast(dummy, ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x1000)
+    o = sslic._Options(0.0, 0, None, None, None, None)
+    S = sslic._i32([16, 16])
+    dims = sslic._i64([64, 64])
+    bad = [
+        dict(channels=0), dict(channels=9), dict(dtype=7), dict(m=0.0), dict(m=float("nan")),
+        dict(iterations=0), dict(image=None), dict(labels=None),
+    ]
+    for b in bad:
+        a = dict(image=fake, ndim=2, channels=3, dtype=0, m=10.0, iterations=5, labels=fake)
+        a.update(b)
+        rc = lib.sslic_run(ctxp, a["image"], a["ndim"], dims, a["channels"], a["dtype"], S, a["m"],
+                           a["iterations"], ctypes.byref(o), a["labels"], fake, None, None, None,
+                           None)
+        assert rc == -1, b
+    o.tol = -1.0
+    rc = lib.sslic_run(ctxp, fake, 2, dims, 3, 0, S, 10.0, 5, ctypes.byref(o), fake, fake, None,
+                       None, None, None)
+    assert rc == -1 and "tol" in lib.sslic_last_error().decode()
+
+
+def test_no_cpu_fallback_without_gpu(lib):
+    """Without a GPU the library reports a device error instead of computing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1806_08741_amd import sslic
+    with pytest.raises(sslic.SslicError):
+        sslic.Context(0)
+    img = torch.zeros((8, 8, 1), dtype=torch.uint8)
+    with pytest.raises(sslic.SslicError, match="GPU"):
+        sslic._geom(img)

@@ -1,0 +1,270 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every test feeds both sides the same seeded bytes.  Bars (stated per test):
+seeding, grid labels, integer updates, counts and connectivity are bit-exact;
+one assignment step from the same centres disagrees on at most 1e-4 of the
+voxels; float32 updates are within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1806_08741_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ASSIGN_TOL = 1e-4     # fraction of voxels whose label may differ after one step
+F32_UPDATE_RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1806_08741_amd import sslic
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sslic.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def f32_exact(cen):
+    """Round centres to float32-representable doubles (both sides see the same
+    window edges and the FP32 path sees no extra rounding of its inputs)."""
+    return cen.astype(np.float32).astype(np.float64)
+
+
+def rand_image(dims, C, dtype, seed, hi=None):
+    rng = np.random.default_rng(seed)
+    shape = tuple(dims[::-1]) + (C,)
+    if dtype == np.float32:
+        return rng.uniform(0, 255 if hi is None else hi, size=shape).astype(np.float32)
+    top = {np.uint8: 255, np.uint16: 65535}[dtype] if hi is None else hi
+    return rng.integers(0, top + 1, size=shape).astype(dtype)
+
+
+def workload(name, dims):
+    return synth.workload_image(name, "cpu", dims=dims).numpy()
+
+
+# geometry cases: several tiles, ragged tails, 1D..4D, generic channel counts
+CASES = [
+    ("rgb-256", (256, 256), (16, 16), 10.0),
+    ("slide-16k", (1000, 777), (16, 16), 10.0),
+    ("fibsem-1k", (90, 77, 65), (8, 8, 8), 20.0),
+    ("rand-u8-c5", (130, 70), (12, 9), 15.0),
+    ("rand-f32-c2", (67, 45, 19), (7, 6, 5), 5.0),
+    ("rand-u16-1d", (3001,), (16,), 10.0),
+    ("rand-u8-4d", (13, 11, 9, 7), (4, 4, 3, 3), 8.0),
+    ("rand-f32-c1", (333, 129), (10, 10), 0.5),
+]
+
+
+def case_image(name, dims):
+    if name in synth.WORKLOADS:
+        return workload(name, dims)
+    kind = name.split("-")
+    dt = {"u8": np.uint8, "u16": np.uint16, "f32": np.float32}[kind[1]]
+    C = int(kind[2][1:]) if kind[2].startswith("c") else (3 if dt == np.uint8 else 1)
+    return rand_image(dims, C, dt, sum(map(ord, name)))
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_seed_bit_exact(ctx, name, dims, S, m):
+    img = case_image(name, dims)
+    nd = len(dims)
+    exp = oracle.seed(img, nd, S)
+    got = host(ctx.seed(dev(img), S))
+    np.testing.assert_array_equal(got, exp)
+
+
+@pytest.mark.parametrize("dims,S", [((1000, 777), (16, 16)), ((90, 77, 65), (8, 8, 8)),
+                                    ((101,), (7,)), ((13, 11, 9, 7), (4, 4, 3, 3))])
+def test_grid_labels_bit_exact(ctx, dims, S):
+    got = host(ctx.grid_labels(dims, S))
+    np.testing.assert_array_equal(got, oracle.grid_labels(dims, S))
+
+
+def oracle_centres_after(img, nd, S, m, iters):
+    r = oracle.run(img, nd, S, m, iters, connectivity=False)
+    return r
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_assign_one_step(ctx, name, dims, S, m):
+    """One assignment step from the same (oracle) centres."""
+    img = case_image(name, dims)
+    nd = len(dims)
+    for iters in (1, 3):
+        r = oracle_centres_after(img, nd, S, m, iters)
+        cen = f32_exact(r["centres"])
+        prev = r["labels"].copy()
+        exp = prev.copy()
+        oracle.assign(img, nd, S, m, cen, exp)
+        got_t = dev(prev)
+        ctx.assign(dev(img), S, m, dev(cen), got_t)
+        got = host(got_t)
+        frac = float((got != exp).mean())
+        assert frac <= ASSIGN_TOL, f"{name}: {frac:.2e} of labels differ after one step"
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_update_one_step(ctx, name, dims, S, m):
+    """Update from the same labels: bit-exact for integer images."""
+    img = case_image(name, dims)
+    nd = len(dims)
+    r = oracle_centres_after(img, nd, S, m, 2)
+    lab = r["labels"]
+    cen0 = r["centres"]
+    exp_c, exp_n, exp_e = oracle.update(img, nd, S, m, lab, cen0)
+    got_c, got_n, got_e = ctx.update(dev(img), S, m, dev(lab), dev(cen0))
+    got_c, got_n, got_e = host(got_c), host(got_n), host(got_e)[0]
+    np.testing.assert_array_equal(got_n, exp_n)
+    if img.dtype == np.float32:
+        np.testing.assert_allclose(got_c, exp_c, rtol=F32_UPDATE_RTOL, atol=0)
+    else:
+        np.testing.assert_array_equal(got_c, exp_c)
+    assert got_e == pytest.approx(exp_e, rel=1e-9)
+
+
+def test_update_arbitrary_labels(ctx):
+    """Random labels (no spatial coherence) and labels outside [0, K) that
+    must be ignored: the LDS table overflows into global atomics."""
+    rng = np.random.default_rng(1)
+    img = rand_image((300, 200), 3, np.uint8, 2)
+    K = 5000
+    lab = rng.integers(-3, K + 3, 60000).astype(np.int32)
+    cen0 = rng.uniform(0, 100, (K, 5))
+    exp_c, exp_n, _ = oracle.update(img, 2, (16, 16), 10.0, lab, cen0)
+    got_c, got_n, _ = ctx.update(dev(img), (16, 16), 10.0, dev(lab), dev(cen0))
+    np.testing.assert_array_equal(host(got_n), exp_n)
+    np.testing.assert_array_equal(host(got_c), exp_c)
+
+
+CC_CASES = [((64, 48), (8, 8)), ((300, 211), (16, 16)), ((40, 33, 27), (6, 6, 6)),
+            ((500,), (9,)), ((9, 8, 7, 6), (3, 3, 3, 2))]
+
+
+@pytest.mark.parametrize("dims,S", CC_CASES)
+def test_connectivity_bit_exact_random_labels(ctx, dims, S):
+    rng = np.random.default_rng(len(dims))
+    K, Ka = oracle.num_clusters(dims, S)
+    lab0 = oracle.grid_labels(dims, S)
+    noise = rng.random(lab0.size) < 0.2
+    lab0[noise] = rng.integers(0, K, int(noise.sum()))
+    nd = len(dims)
+    cen = np.zeros((K, 1 + nd))
+    cen[:, 1:] = rng.uniform(-1, 1, (K, nd)) * 0.5 + np.stack(
+        np.meshgrid(*[(np.arange(k) + 0.5) * d / k for k, d in zip(Ka, dims)], indexing="ij"),
+        -1).reshape(-1, nd, order="F")
+    exp = lab0.copy()
+    nl = oracle.connectivity(dims, S, cen, 1, exp)
+    got = dev(lab0)
+    gnl = ctx.connectivity(dims, S, dev(cen), 1, got)
+    np.testing.assert_array_equal(host(got), exp)
+    assert gnl == nl
+
+
+def test_connectivity_golden_cases(ctx):
+    import glob
+    import json
+    import os
+    for path in sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "cc_*.json"))):
+        case = json.load(open(path))
+        lab = np.array([[int(v) for v in r.split()] for r in case["labels"]], dtype=np.int32).ravel()
+        exp = np.array([[int(v) for v in r.split()] for r in case["expected"]], dtype=np.int32).ravel()
+        t = dev(lab)
+        nl = ctx.connectivity(case["dims"], case["S"], dev(np.array(case["centres"])), case["C"], t)
+        np.testing.assert_array_equal(host(t), exp, err_msg=path)
+        assert nl == case["n_labels"]
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES[:4])
+def test_connectivity_after_run(ctx, name, dims, S, m):
+    img = case_image(name, dims)
+    nd = len(dims)
+    r = oracle.run(img, nd, S, m, 5, connectivity=False)
+    exp = r["labels"].copy()
+    C = img.shape[-1]
+    nl = oracle.connectivity(dims, S, r["centres"], C, exp)
+    got = dev(r["labels"])
+    gnl = ctx.connectivity(dims, S, dev(r["centres"]), C, got)
+    np.testing.assert_array_equal(host(got), exp)
+    assert gnl == nl
+
+
+# ---------------------------------------------------------------------------
+# closed forms through the whole GPU run
+
+def test_run_constant_image_closed_form(ctx):
+    img = np.full((48, 64, 3), 77, np.uint8)
+    exp = oracle.run(img, 2, (16, 8), 10.0, 4)
+    got = ctx.run(dev(img), (16, 8), 10.0, 4, residuals=True)
+    np.testing.assert_array_equal(host(got["labels"]), exp["labels"])
+    np.testing.assert_array_equal(host(got["centres"]), exp["centres"])
+    assert got["n_labels"] == exp["n_labels"]
+    np.testing.assert_allclose(host(got["residuals"]), exp["residuals"], rtol=1e-12)
+
+
+def test_run_grid_aligned_regions(ctx):
+    dims, S = (48, 36, 24), (8, 6, 8)
+    rng = np.random.default_rng(4)
+    Ka = [d // s for d, s in zip(dims, S)]
+    K = int(np.prod(Ka))
+    from tests import brute
+    X = brute.coords(dims)
+    cell = np.zeros(X.shape[0], dtype=np.int64)
+    st = 1
+    for i in range(3):
+        cell += (X[:, i] // S[i]) * st
+        st *= Ka[i]
+    cols = rng.permutation(np.arange(1, K + 1) * 25)[:, None].astype(np.uint16)
+    img = cols[cell].reshape(tuple(dims[::-1]) + (1,))
+    exp = oracle.run(img, 3, S, 10.0, 3)
+    got = ctx.run(dev(img), S, 10.0, 3)
+    np.testing.assert_array_equal(host(got["labels"]), exp["labels"])
+    np.testing.assert_array_equal(host(got["centres"]), exp["centres"])
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_run_end_to_end(ctx, name, dims, S, m):
+    """Whole filter.  Per-step agreement compounds over iterations, so this
+    reports agreement and checks it stays high; exactness is per step."""
+    img = case_image(name, dims)
+    nd = len(dims)
+    exp = oracle.run(img, nd, S, m, 5, connectivity=True)
+    got = ctx.run(dev(img), S, m, 5, connectivity=True, residuals=True)
+    gl = host(got["labels"])
+    agree = float((gl == exp["labels"]).mean())
+    assert got["iterations"] == 5
+    assert 0 <= gl.min() and gl.max() < got["n_labels"]
+    assert agree >= 0.99, f"{name}: end-to-end label agreement {agree:.5f}"
+    np.testing.assert_allclose(host(got["residuals"]), exp["residuals"], rtol=5e-2)
+
+
+def test_run_tol_stops_on_device(ctx):
+    img = np.full((64, 64, 1), 5, np.uint16)
+    got = ctx.run(dev(img), (8, 8), 10.0, 10, tol=1e-9, residuals=True)
+    exp = oracle.run(img, 2, (8, 8), 10.0, 10, tol=1e-9)
+    assert got["iterations"] == exp["iterations"] == 2
+    np.testing.assert_array_equal(host(got["labels"]), exp["labels"])
+
+
+def test_run_init_centres_resume(ctx):
+    """Resuming from the centres after 2 iterations equals one 2+3 run's
+    centres up to the per-step assignment tolerance."""
+    img = workload("rgb-256", (256, 256))
+    a = oracle.run(img, 2, (16, 16), 10.0, 2, connectivity=False)
+    got = ctx.run(dev(img), (16, 16), 10.0, 3, connectivity=False,
+                  init_centres=dev(f32_exact(a["centres"])))
+    exp = oracle.run(img, 2, (16, 16), 10.0, 3, connectivity=False,
+                     init_centres=f32_exact(a["centres"]))
+    agree = float((host(got["labels"]) == exp["labels"]).mean())
+    assert agree >= 0.999
