@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the SSLIC hot path on one MI355X.
+
+One step is one whole ``sslic_run`` (seeding, every iteration of assignment +
+update + residual test, and connectivity when the workload asks for it) over
+a synthetic image already resident in HBM.  The default workload is the
+slide-like 2D RGB uint8 16384x16384 image (S=16, m=10, 10 iterations, no
+connectivity).  Prints one JSON line:
+
+  value          Mvoxel*iter/s = voxels * iterations * steps / timed seconds
+  roofline       the dominant kernel's algorithmic bytes per launch / its mean
+                 launch time (HIP events on the launch stream, timed region),
+                 against the 8 TB/s HBM peak; ``traffic`` comes from committed
+                 rocprofv3 FETCH_SIZE/WRITE_SIZE counters when they were taken
+                 on the current kernel source, else null
+  cpu_baseline   the FP64 oracle (single thread) on a crop of the same image
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES = {"u8": 1, "u16": 2, "f32": 4}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources a kernel class is built from (for counter staleness)."""
+    files = {"sweep": ["sweep.hip", "sslic_internal.h"],
+             "update": ["update.hip", "sslic_internal.h"]}[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1806_08741_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from profiles/traffic_<kernel>_<workload>.json, if
+    the counters were taken on the current source of that kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(img_gpu, w, crop):
+    """The oracle as it stands, one thread, on the top-left crop x crop voxels
+    of the same image; returns (Mvoxel*iter/s, seconds, description)."""
+    import numpy as np
+    import oracle
+    sub = img_gpu[:crop, :crop].contiguous().cpu().numpy()
+    t0 = time.perf_counter()
+    r = oracle.run(sub, 2, w.S, w.m, w.iterations, connectivity=w.connectivity)
+    dt = time.perf_counter() - t0
+    vox = sub.shape[0] * sub.shape[1]
+    assert r["iterations"] == w.iterations
+    return vox * w.iterations / dt / 1e6, dt, f"top-left {crop}x{crop} crop, {w.iterations} iterations"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="slide-16k")
+    ap.add_argument("--cpu-crop", type=int, default=4096,
+                    help="side of the crop the CPU oracle is timed on (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent images shard with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_08741_amd import sslic, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X GPU", file=sys.stderr)
+        sys.exit(1)
+    w = synth.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    img = synth.workload_image(w.name, dev)
+    torch.cuda.synchronize()
+    print(f"[bench] generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    ctx = sslic.Context(0)
+    N = w.voxels
+    K = sslic.num_clusters(w.dims, w.S)
+    out = {"labels": torch.empty(N, dtype=torch.int32, device=dev),
+           "centres": torch.empty((K, w.channels + len(w.dims)), dtype=torch.float64, device=dev),
+           "counts": torch.empty(K, dtype=torch.int64, device=dev)}
+
+    def step():
+        ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity, out=out, sync=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    L = sslic.lib()
+    import ctypes
+    sslic._check(L.sslic_profile_enable(ctx._h, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {}
+    for k in ("seed", "bins", "sweep", "finalize", "connectivity"):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        sslic._check(L.sslic_profile_read(ctx._h, k.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        if n.value:
+            prof[k] = {"ms_total": ms.value, "launches": n.value, "ms_mean": ms.value / n.value}
+    sslic._check(L.sslic_profile_enable(ctx._h, 0))
+    print(f"[bench] timed {args.steps} steps in {dt:.3f}s; kernels: "
+          + ", ".join(f"{k} {v['ms_mean']:.3f} ms" for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+
+    # sanity: the timed result is a labelling of the whole image
+    lab = out["labels"]
+    assert int(lab.min()) >= 0 and int(lab.max()) < K
+
+    ms_step = dt / args.steps * 1e3
+    value = N * w.iterations * args.steps / dt / 1e6
+    dt_name = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}[w.dtype]
+    # the sweep (assignment + map step) reads the image once and writes the labels once
+    per_vox = w.channels * BYTES[dt_name] + 4
+    dom = "sweep"
+    bytes_launch = N * per_vox
+    achieved = bytes_launch / (prof[dom]["ms_mean"] * 1e-3) / 1e9
+    traffic = load_traffic(dom, w.name)
+    rec = {
+        "metric": "SLIC Mvoxel*iter/s (whole sslic_run per step; inputs resident in HBM)",
+        "value": round(value, 1),
+        "unit": "Mvoxel*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(w.dims), "channels": w.channels,
+                   "image_dtype": dt_name, "S": list(w.S), "m": w.m,
+                   "iterations": w.iterations, "connectivity": w.connectivity, "K": K,
+                   "recipe": w.recipe},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch},
+        "kernels_ms": {k: round(v["ms_mean"], 4) for k, v in prof.items()},
+    }
+    if args.cpu_crop > 0:
+        v, sec, desc = cpu_baseline(img, w, min(args.cpu_crop, w.dims[0]))
+        rec["cpu_baseline"] = {"value": round(v, 3), "unit": "Mvoxel*iter/s", "cores": 1,
+                               "kind": "oracle", "sample": desc, "seconds": round(sec, 2)}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,10 +4,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/sslic.h"
+#include "../../include/sslic_profile.h"
 #include "../../include/sslic_steps.h"
 #include "sslic_internal.h"
 
@@ -18,6 +22,11 @@ struct sslic_ctx {
   char* ws = nullptr;   // device workspace
   size_t ws_size = 0;
   int32_t* host_ints = nullptr;  // pinned staging for *_out scalars
+  // event timing of kernel classes (sslic_profile.h)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> marks;
 };
 
 namespace {
@@ -79,9 +88,9 @@ int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, con
     g->bst[i] = nbins;
     nbins *= g->nb[i];
     prodS *= s;
-    double w = (m * m) / ((double)s * (double)s);
-    g->wd[i] = w;
-    g->w[i] = (float)w;
+    g->wd[i] = (m * m) / ((double)s * (double)s);
+    g->swd[i] = m / (double)s;
+    g->sw[i] = (float)g->swd[i];
   }
   g->N = N;
   g->K = K_override > 0 ? K_override : K;
@@ -98,11 +107,11 @@ constexpr size_t kAlign = 256;
 size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part, acc, res_acc, flags;
+  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, brec, scan_part, acc, part, res_acc, flags;
   size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, total;
 };
 
-Layout layout(const Geo& g, int iterations, bool cc) {
+Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   Layout L{};
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -115,8 +124,10 @@ Layout layout(const Geo& g, int iterations, bool cc) {
   L.bin_cnt = put((size_t)g.nbins * 4);
   L.bin_start = put((size_t)(g.nbins + 1) * 4);
   L.bin_items = put((size_t)g.K * 4);
+  L.brec = put((size_t)g.K * g.rs * 4);
   L.scan_part = put((size_t)(g.nbins / 4096 + 2) * 4);
   L.acc = put((size_t)g.K * g.F * 8);
+  L.part = put(part ? (size_t)g.K * ((size_t)1 << g.nd) * g.F * 8 : 0);
   L.res_acc = put((size_t)2 * (iterations > 0 ? iterations : 1) * 8);
   L.flags = put(64);
   if (cc) {
@@ -157,8 +168,10 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L) {
   it.bin_cnt = (int32_t*)(b + L.bin_cnt);
   it.bin_start = (int32_t*)(b + L.bin_start);
   it.bin_items = (int32_t*)(b + L.bin_items);
+  it.brec = (float*)(b + L.brec);
   it.scan_part = (int32_t*)(b + L.scan_part);
   it.acc = (uint64_t*)(b + L.acc);
+  it.part = (uint64_t*)(b + L.part);
   it.res_acc = (double*)(b + L.res_acc);
   it.done = (int32_t*)(b + L.flags);
   it.iters = it.done + 1;
@@ -184,6 +197,33 @@ int select_device(sslic_ctx* ctx) {
   return SSLIC_OK;
 }
 
+hipEvent_t next_event(sslic_ctx* ctx) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[ctx->ev_used++];
+}
+
+// Brackets the launches of one kernel class with events when profiling.
+struct Mark {
+  sslic_ctx* ctx;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Mark(sslic_ctx* c, const char* n, hipStream_t st) : ctx(c), name(n), s(st) {
+    if (ctx && ctx->prof && (a = next_event(ctx))) (void)hipEventRecord(a, s);
+  }
+  ~Mark() {
+    if (!a) return;
+    hipEvent_t b = next_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    ctx->marks[name].emplace_back(a, b);
+  }
+};
+
 // Copy device int32 scalars to host outputs (waits for the stream).
 int read_ints(sslic_ctx* ctx, hipStream_t s, const int32_t* dev_a, int32_t* out_a,
               const int32_t* dev_b, int32_t* out_b) {
@@ -198,20 +238,31 @@ int read_ints(sslic_ctx* ctx, hipStream_t s, const int32_t* dev_a, int32_t* out_
 
 // The iteration loop of one image on the context workspace.  Centres are in
 // `cen` (seeded or given) when called.
-int run_iterations(const Geo& g, const Iter& it, const void* image, int iterations, double tol,
-                   int32_t* labels, double* cen, int64_t* counts, double* residuals, hipStream_t s) {
+int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* image, int iterations,
+                   double tol, int32_t* labels, double* cen, int64_t* counts, double* residuals,
+                   hipStream_t s) {
+  const int slots = sweep_slots(g);
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
+  if (slots) HIP_TRY(launch_fill_u64(it.part, 0, g.K * ((int64_t)1 << g.nd) * g.F, s));
   HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * iterations, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
   HIP_TRY(launch_prep(g, cen, it, s));
   for (int t = 0; t < iterations; ++t) {
-    HIP_TRY(launch_bins(g, it, s));
-    HIP_TRY(launch_assign(g, image, it, labels, t == 0, s));
-    HIP_TRY(launch_update(g, image, labels, it, s));
-    HIP_TRY(launch_finalize(g, cen, counts, it, t, t + 1 < iterations, s));
-    HIP_TRY(launch_residual_finish(it, t, tol, residuals, s));
+    {
+      Mark mk(ctx, "bins", s);
+      HIP_TRY(launch_bins(g, it, s));
+    }
+    {
+      Mark mk(ctx, "sweep", s);
+      HIP_TRY(launch_sweep(g, image, it, labels, t == 0, 1, s));
+    }
+    {
+      Mark mk(ctx, "finalize", s);
+      HIP_TRY(launch_finalize(g, cen, counts, it, t, t + 1 < iterations, slots, s));
+      HIP_TRY(launch_residual_finish(it, t, tol, residuals, s));
+    }
   }
   return SSLIC_OK;
 }
@@ -248,6 +299,7 @@ void sslic_destroy(sslic_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->host_ints) (void)hipHostFree(ctx->host_ints);
   delete ctx;
@@ -279,7 +331,7 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
   const bool cc = !o.no_connectivity;
-  Layout L = layout(g, iterations, cc);
+  Layout L = layout(g, iterations, cc, true);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Iter it = iter_view(ctx, L);
@@ -288,12 +340,15 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
       HIP_TRY(hipMemcpyAsync(centres, o.init_centres, (size_t)g.K * g.row * 8,
                              hipMemcpyDeviceToDevice, s));
   } else {
+    Mark mk(ctx, "seed", s);
     HIP_TRY(launch_seed(g, image, centres, s));
   }
-  if ((rc = run_iterations(g, it, image, iterations, o.tol, labels, centres, counts, o.residuals, s)))
+  if ((rc = run_iterations(ctx, g, it, image, iterations, o.tol, labels, centres, counts,
+                           o.residuals, s)))
     return rc;
   int32_t* nl = nlab_slot(ctx, L);
   if (cc) {
+    Mark mk(ctx, "connectivity", s);
     HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
   } else {
     HIP_TRY(launch_fill_i32(nl, (int32_t)g.K, 1, s));
@@ -354,7 +409,7 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, K);
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
-  Layout L = layout(g, 1, false);
+  Layout L = layout(g, 1, false, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Iter it = iter_view(ctx, L);
@@ -362,7 +417,7 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_prep(g, centres, it, s));
   HIP_TRY(launch_bins(g, it, s));
-  HIP_TRY(launch_assign(g, image, it, labels, 0, s));
+  HIP_TRY(launch_sweep(g, image, it, labels, 0, 0, s));
   return SSLIC_OK;
 }
 
@@ -375,7 +430,7 @@ int sslic_update(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, K);
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
-  Layout L = layout(g, 1, false);
+  Layout L = layout(g, 1, false, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Iter it = iter_view(ctx, L);
@@ -383,7 +438,7 @@ int sslic_update(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_update(g, image, labels, it, s));
-  HIP_TRY(launch_finalize(g, centres, counts, it, 0, 0, s));
+  HIP_TRY(launch_finalize(g, centres, counts, it, 0, 0, 0, s));
   HIP_TRY(launch_residual_finish(it, 0, -1.0, residual, s));
   return SSLIC_OK;
 }
@@ -397,13 +452,51 @@ int sslic_connectivity(sslic_ctx* ctx, int ndim, const int64_t* dims, const int3
   int rc = make_geo(&g, ndim, dims, channels, kU8, S, 1.0, K);
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
-  Layout L = layout(g, 1, true);
+  Layout L = layout(g, 1, true, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   int32_t* nl = nlab_slot(ctx, L);
   HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
   if (n_labels_dev) HIP_TRY(hipMemcpyAsync(n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
   return read_ints(ctx, s, nl, n_labels_out, nullptr, nullptr);
+}
+
+int sslic_profile_enable(sslic_ctx* ctx, int enable) {
+  if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
+  int rc = select_device(ctx);
+  if (rc) return rc;
+  if (enable) {
+    HIP_TRY(hipDeviceSynchronize());  // recorded events may still be pending
+    ctx->marks.clear();
+    ctx->ev_used = 0;
+  }
+  ctx->prof = enable != 0;
+  return SSLIC_OK;
+}
+
+int sslic_profile_read(sslic_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel) return fail(SSLIC_EINVAL, "ctx and kernel must be given");
+  int rc = select_device(ctx);
+  if (rc) return rc;
+  double tot = 0.0;
+  int64_t n = 0;
+  auto f = ctx->marks.find(kernel);
+  if (f != ctx->marks.end()) {
+    for (auto& pr : f->second) {
+      HIP_TRY(hipEventSynchronize(pr.second));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot += ms;
+      ++n;
+    }
+    f->second.clear();
+  }
+  bool empty = true;
+  for (auto& kv : ctx->marks) empty = empty && kv.second.empty();
+  if (empty) ctx->ev_used = 0;
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
+  return SSLIC_OK;
 }
 
 }  // extern "C"

@@ -11,6 +11,10 @@ namespace {
 
 constexpr int kThreads = 256;
 
+struct TileDims {
+  int T[kMaxDim];
+};
+
 inline int blocks_for(int64_t n, int per = kThreads) { return (int)((n + per - 1) / per); }
 
 template <typename T>
@@ -144,7 +148,7 @@ __device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_
   int64_t bin = 0;
   for (int i = 0; i < g.nd; ++i) {
     double ci = i < g.nd_out ? row[g.C + i] : 0.0;
-    rec[g.C + i] = (float)ci;
+    rec[g.C + i] = (float)(ci * g.swd[i]);
     int lo, hi;
     if (isfinite(ci)) {
       double l = ceil(ci - (double)g.S[i]);
@@ -163,6 +167,7 @@ __device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_
     b = min(max(b, 0), g.nb[i] - 1);
     bin += b * g.bst[i];
   }
+  irec[g.C + 3 * g.nd] = (int32_t)k;
   it.bin_of[k] = (int32_t)bin;
   atomicAdd(&it.bin_cnt[bin], 1);
 }
@@ -272,6 +277,16 @@ __global__ void binsort_kernel(Geo g, Iter it) {
   it.bin_cnt[b] = 0;
 }
 
+// Records in bin order, so that a bin's centres are read contiguously.
+__global__ void binrec_kernel(Geo g, Iter it) {
+  if (*it.done) return;
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= g.K) return;
+  const float4* src = reinterpret_cast<const float4*>(it.ctab + (int64_t)it.bin_items[j] * g.rs);
+  float4* dst = reinterpret_cast<float4*>(it.brec + j * g.rs);
+  for (int q = 0; q < g.rs / 4; ++q) dst[q] = src[q];
+}
+
 // ---------------------------------------------------------------------------
 // Update, final step: sums / count in FP64 (correctly rounded, as the oracle),
 // the residual term of the cluster, counts out, accumulators reset, and the
@@ -283,27 +298,61 @@ __device__ __forceinline__ double warp_sum(double v) {
 }
 
 __global__ void finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts,
-                                Iter it, int t, int prep_next) {
+                                Iter it, int t, int prep_next, int use_part, TileDims td) {
   if (*it.done) return;
   __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double e_sum = 0.0, e_cnt = 0.0;
   if (k < g.K) {
+    const bool flt = g.dtype == kF32;
     uint64_t* a = it.acc + k * g.F;
-    uint64_t n = a[0];
+    uint64_t si[1 + kMaxDim + kMaxChan];
+    double sf[kMaxChan];
+    for (int f = 0; f < g.F; ++f) {
+      si[f] = a[f];
+      a[f] = 0;
+    }
+    for (int c = 0; c < g.C; ++c) sf[c] = __longlong_as_double((long long)si[1 + g.nd + c]);
+    if (use_part) {
+      // the slots of the tiles this cluster's window meets (as the sweep chose them)
+      const int32_t* irec = reinterpret_cast<const int32_t*>(it.ctab + k * g.rs);
+      int lo[kMaxDim], hi[kMaxDim], t0[kMaxDim];
+      for (int i = 0; i < g.nd; ++i) {
+        lo[i] = max(irec[g.C + g.nd + i], 0);
+        hi[i] = min(irec[g.C + 2 * g.nd + i], g.n[i] - 1);
+        t0[i] = lo[i] / td.T[i];
+      }
+      const int ns = 1 << g.nd;
+      for (int q = 0; q < ns; ++q) {
+        bool meets = true;
+        for (int i = 0; i < g.nd; ++i) {
+          const int tlo = (t0[i] + ((q >> i) & 1)) * td.T[i];
+          meets = meets && lo[i] <= hi[i] && tlo <= hi[i] && tlo + td.T[i] - 1 >= lo[i];
+        }
+        if (!meets) continue;
+        uint64_t* p = it.part + (k * ns + q) * g.F;
+        for (int f = 0; f < 1 + g.nd; ++f) si[f] += p[f];
+        for (int c = 0; c < g.C; ++c) {
+          const uint64_t raw = p[1 + g.nd + c];
+          if (flt) sf[c] += __longlong_as_double((long long)raw);
+          else si[1 + g.nd + c] += raw;
+        }
+        for (int f = 0; f < g.F; ++f) p[f] = 0;
+      }
+    }
+    const uint64_t n = si[0];
     double* row = cen + k * g.row;
     if (n > 0) {
       double dn = (double)n;
       double e = 0.0;
       for (int c = 0; c < g.C; ++c) {
-        uint64_t raw = a[1 + g.nd + c];
-        double nv = g.dtype == kF32 ? __longlong_as_double((long long)raw) / dn : (double)raw / dn;
+        double nv = flt ? sf[c] / dn : (double)si[1 + g.nd + c] / dn;
         double d = nv - row[c];
         e = e + d * d;
         row[c] = nv;
       }
       for (int i = 0; i < g.nd_out; ++i) {
-        double nv = (double)a[1 + i] / dn;
+        double nv = (double)si[1 + i] / dn;
         double d = nv - row[g.C + i];
         e = e + g.wd[i] * (d * d);
         row[g.C + i] = nv;
@@ -312,7 +361,6 @@ __global__ void finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __rest
       e_cnt = 1.0;
     }
     if (counts) counts[k] = (int64_t)n;
-    for (int f = 0; f < g.F; ++f) a[f] = 0;
     if (prep_next) prep_one(g, row, k, it);
   }
   e_sum = warp_sum(e_sum);
@@ -379,12 +427,16 @@ hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s) {
   scan_add_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(it.bin_start, it.scan_part, g.nbins, it.done);
   scatter_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, it);
   binsort_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(g, it);
+  binrec_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, it);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Iter& it, int t,
-                           int prep_next, hipStream_t s) {
-  finalize_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, counts, it, t, prep_next);
+                           int prep_next, int use_part, hipStream_t s) {
+  TileDims td{};
+  sweep_tile_shape(g.nd, td.T);
+  finalize_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, counts, it, t, prep_next,
+                                                       use_part, td);
   return hipGetLastError();
 }
 

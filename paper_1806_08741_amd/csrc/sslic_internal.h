@@ -31,7 +31,8 @@ struct Geo {
   int nb[kMaxDim];   // S-bins per axis = ceil(n / S)
   int64_t bst[kMaxDim];  // bin stride per axis
   int64_t nbins;
-  float w[kMaxDim];  // (m / S_i)^2 in FP32 (assignment distance)
+  float sw[kMaxDim]; // m / S_i in FP32: coordinates are scaled by it in the assignment
+  double swd[kMaxDim];  // m / S_i in FP64
   double wd[kMaxDim];  // (m / S_i)^2 in FP64 (residual)
   int rs;            // words per record of the assignment centre table
   int64_t prodS;     // prod S_i (connectivity threshold 4 size > prodS)
@@ -41,11 +42,13 @@ struct Geo {
 
 // Record k of the assignment centre table (FP32 words, stride g.rs):
 //   [0, C)            channel means mu_c
-//   [C, C+nd)         coordinates c_i
+//   [C, C+nd)         scaled coordinates c'_i = c_i * m / S_i (rounded from FP64)
 //   [C+nd, C+2nd)     int32 lo_i = ceil(c_i - S_i)   (FP64, clamped)
 //   [C+2nd, C+3nd)    int32 hi_i = floor(c_i + S_i)
-// so that x is inside the closed window of k iff lo_i <= x_i <= hi_i.
-__host__ __device__ inline int rec_words(int C, int nd) { return (C + 3 * nd + 3) & ~3; }
+//   [C+3nd]           int32 cluster index k
+// so that x is inside the closed window of k iff lo_i <= x_i <= hi_i, and
+// D^2(x, k) = sum_i (x_i * m / S_i - c'_i)^2 + sum_c (I_c(x) - mu_c)^2.
+__host__ __device__ inline int rec_words(int C, int nd) { return (C + 3 * nd + 1 + 3) & ~3; }
 
 // Device buffers used by one iteration loop.
 struct Iter {
@@ -53,9 +56,11 @@ struct Iter {
   int32_t* bin_of;    // [K]
   int32_t* bin_cnt;   // [nbins]   counts, then cursors; zero between uses
   int32_t* bin_start; // [nbins + 1]
-  int32_t* bin_items; // [K]
+  int32_t* bin_items; // [K]     cluster indices in bin order (ascending within a bin)
+  float* brec;        // [K][rs]  their records, in the same order
   int32_t* scan_part; // [ceil(nbins / 4096) + 1]
-  uint64_t* acc;      // [K][F]    zero between uses
+  uint64_t* acc;      // [K][F]    zero between uses (atomic sums)
+  uint64_t* part;     // [K][2^nd][F] per-tile sums from the sweep; zero between uses
   double* res_acc;    // [2 * iterations]  (sum, count) per iteration
   int32_t* done;      // converged flag: kernels return early when set
   int32_t* iters;     // iterations run
@@ -75,14 +80,33 @@ hipError_t launch_prep(const Geo& g, const double* cen, const Iter& it, hipStrea
 // bin counts -> CSR (bin_start, bin_items sorted by cluster index)
 hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s);
 
-hipError_t launch_assign(const Geo& g, const void* img, const Iter& it, int32_t* labels,
-                         int first, hipStream_t s);
+// Arguments of the fused assignment + map sweep (sweep.hip).
+struct SweepArgs {
+  const int32_t* bstart;
+  const float* brec;
+  const float* ctab;
+  int32_t* labels;
+  int first;
+  const int32_t* done;
+  uint64_t* part;
+  uint64_t* acc;
+  int ntiles;
+  int nt[kMaxDim];
+  int slots;  // 1: per-cluster tile slots; 0: tiles narrower than a window, atomics only
+};
+// assignment of every voxel (labels); with `accumulate`, also the per-cluster
+// sums into it.part (tile slots) / it.acc (atomics)
+hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels,
+                        int first, int accumulate, hipStream_t s);
+int sweep_slots(const Geo& g);              // whether the sweep uses tile slots
+void sweep_tile_shape(int nd, int* T);      // its tile extent per axis
 hipError_t launch_update(const Geo& g, const void* img, const int32_t* labels,
                          const Iter& it, hipStream_t s);
-// accumulators -> new centres, counts, residual partials; then prep for the
-// next iteration (table, bins) when `prep_next`
+// accumulators (and, with `use_part`, the sweep's tile slots) -> new centres,
+// counts, residual partials; then prep for the next iteration (table, bins)
+// when `prep_next`
 hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Iter& it,
-                           int t, int prep_next, hipStream_t s);
+                           int t, int prep_next, int use_part, hipStream_t s);
 // residual of iteration t -> residuals[t] (if non-null), done flag, iteration count
 hipError_t launch_residual_finish(const Iter& it, int t, double tol, double* residuals,
                                   hipStream_t s);

@@ -1,0 +1,463 @@
+// sweep.hip -- one pass over the image per iteration: the assignment step
+// (Sec. 2.1 distance, Sec. 3.1 stage 2) and the map half of the update (per
+// cluster sums of [1, x, I(x)]) in the same kernel, so the image is read once
+// and the labels written once per iteration.
+//
+// Work decomposition
+//   * A workgroup owns a tile (2D 64x64, 3D 32x32x32, 4D 16x16x8x8); each of
+//     its four waves sweeps a run of blocks of 64 voxels (8x8, 4x4x4,
+//     4x4x2x2) along axis 0.
+//   * For a block, lane i loads the bounds of the i-th centre record in the
+//     bins within one bin of the block (records are stored in bin order, so a
+//     row of bins is one contiguous range), tests whether its window meets the
+//     block and on which axes it cuts it, and a ballot keeps the meeting ones.
+//     The wave then takes them one by one (s_ff1 on the ballot) and reads each
+//     record with scalar loads, so the means and scaled coordinates are
+//     scalar operands of the distance arithmetic:
+//       D^2 = sum_i (x_i m / S_i - c'_i)^2 + sum_c (I_c - mu_c)^2   (FP32).
+//     Centres are visited in raster order of their bins; while cluster indices
+//     keep increasing a strict "<" keeps the lowest index among equal
+//     distances, otherwise the index is compared as well.
+//   * Each lane keeps a running sum for its current label across the blocks
+//     of its run (labels are spatially coherent); when the label changes the
+//     run is added to a per-tile LDS table keyed by label.
+//   * At the end the table goes to global memory without atomics: each
+//     cluster has 2^n slots, one per tile its window can meet (a window spans
+//     at most two tiles per axis when the tile is at least 2S+1 wide), chosen
+//     by the tile's offset from the tile that holds the window's low corner.
+//     Sums for labels outside the window's tiles (voxels that no window
+//     reached keep an older label) and every sum when the tiles are too small
+//     for slots go through 64-bit atomics into the plain accumulators instead.
+#include "sslic_internal.h"
+
+namespace sslic {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+template <int ND>
+struct SweepShape;
+template <>
+struct SweepShape<2> {
+  static constexpr int T[2] = {64, 64};
+  static constexpr int B[2] = {8, 8};
+  static constexpr int kHash = 256;
+};
+template <>
+struct SweepShape<3> {
+  static constexpr int T[3] = {32, 32, 32};
+  static constexpr int B[3] = {4, 4, 4};
+  static constexpr int kHash = 512;
+};
+template <>
+struct SweepShape<4> {
+  static constexpr int T[4] = {16, 16, 8, 8};
+  static constexpr int B[4] = {4, 4, 2, 2};
+  static constexpr int kHash = 512;
+};
+
+template <int ND>
+__host__ __device__ constexpr int blocks_per_tile() {
+  int n = 1;
+  for (int i = 0; i < ND; ++i) n *= SweepShape<ND>::T[i] / SweepShape<ND>::B[i];
+  return n;
+}
+
+__device__ __forceinline__ int grid_label(const Geo& g, const int* x, int nd) {
+  int64_t kk = 0, kst = 1;
+  for (int i = 0; i < nd; ++i) {
+    kk += ((int64_t)x[i] * g.Ka[i] / g.n[i]) * kst;
+    kst *= g.Ka[i];
+  }
+  return (int)kk;
+}
+
+template <bool FLT>
+struct RunSum {
+  using type = uint32_t;
+};
+template <>
+struct RunSum<true> {
+  using type = double;
+};
+
+template <typename T, int ND, int CC, bool ACC>
+__global__ void __launch_bounds__(kThreads)
+sweep_kernel(Geo g, const T* __restrict__ img, SweepArgs a) {
+  if (*a.done) return;
+  using SS = SweepShape<ND>;
+  constexpr int CM = CC > 0 ? CC : kMaxChan;
+  constexpr int RW = (CM + 3 * ND + 1 + 3) & ~3;
+  constexpr int HS = SS::kHash;
+  constexpr int FM = 1 + ND + CM;
+  constexpr int NBW = blocks_per_tile<ND>() / kWaves;
+  constexpr bool FLT = std::is_same<T, float>::value;
+  using RT = typename RunSum<FLT>::type;
+  const int C = CC > 0 ? CC : g.C;
+  const int RS = CC > 0 ? RW : g.rs;
+  const int F = 1 + ND + C;
+
+  __shared__ int s_keys[ACC ? HS : 1];
+  __shared__ uint64_t s_vals[ACC ? HS * FM : 1];
+
+  const int per = (int)(gridDim.x / 8);
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= a.ntiles) return;
+  const int tid = threadIdx.x, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+
+  if constexpr (ACC) {
+    for (int i = tid; i < HS; i += kThreads) s_keys[i] = -1;
+    for (int i = tid; i < HS * F; i += kThreads) s_vals[i] = 0;
+    __syncthreads();
+  }
+
+  int to[ND], tc[ND];
+  {
+    int r = tile;
+    for (int i = 0; i < ND; ++i) {
+      tc[i] = r % a.nt[i];
+      r /= a.nt[i];
+      to[i] = tc[i] * SS::T[i];
+    }
+  }
+  int lx[ND];
+  {
+    int r = lane;
+    for (int i = 0; i < ND; ++i) {
+      lx[i] = r % SS::B[i];
+      r /= SS::B[i];
+    }
+  }
+
+  // running sum of this lane's current label (coordinates relative to the tile)
+  int cur = -1;
+  uint32_t rcnt = 0;
+  uint32_t rco[ND];
+  RT rch[CM];
+  for (int i = 0; i < ND; ++i) rco[i] = 0;
+  for (int c = 0; c < C; ++c) rch[c] = 0;
+
+  auto flush = [&]() {
+    if (cur < 0 || rcnt == 0) return;
+    uint32_t h = ((uint32_t)cur * 2654435761u) >> 8;
+    int slot = -1;
+    for (int p = 0; p < HS; ++p) {
+      h &= HS - 1;
+      const int old = atomicCAS(&s_keys[h], -1, cur);
+      if (old == -1 || old == cur) {
+        slot = (int)h;
+        break;
+      }
+      ++h;
+    }
+    if (slot >= 0) {
+      unsigned long long* vv = reinterpret_cast<unsigned long long*>(s_vals + slot * F);
+      atomicAdd(vv, (unsigned long long)rcnt);
+      for (int i = 0; i < ND; ++i) atomicAdd(vv + 1 + i, (unsigned long long)rco[i]);
+      for (int c = 0; c < C; ++c) {
+        if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(vv + 1 + ND + c), (double)rch[c]);
+        else atomicAdd(vv + 1 + ND + c, (unsigned long long)rch[c]);
+      }
+    } else {  // table full: global accumulators (coordinates made absolute)
+      unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)cur * F);
+      atomicAdd(gg, (unsigned long long)rcnt);
+      for (int i = 0; i < ND; ++i)
+        atomicAdd(gg + 1 + i, (unsigned long long)rco[i] + (unsigned long long)rcnt * to[i]);
+      for (int c = 0; c < C; ++c) {
+        if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(gg + 1 + ND + c), (double)rch[c]);
+        else atomicAdd(gg + 1 + ND + c, (unsigned long long)rch[c]);
+      }
+    }
+  };
+
+  for (int q = 0; q < NBW; ++q) {
+    // block origin (global) and extent
+    int blo[ND], bhi[ND], x[ND];
+    bool inside = true, valid = true;
+    {
+      int r = wave * NBW + q;
+      for (int i = 0; i < ND; ++i) {
+        const int nbk = SS::T[i] / SS::B[i];
+        blo[i] = to[i] + (r % nbk) * SS::B[i];
+        r /= nbk;
+        inside = inside && blo[i] < g.n[i];
+        bhi[i] = min(blo[i] + SS::B[i], g.n[i]) - 1;
+        x[i] = blo[i] + lx[i];
+        valid = valid && x[i] <= bhi[i];
+      }
+    }
+    if (!inside) continue;
+    int64_t v = 0, v0 = 0;
+    float xs[ND];
+    for (int i = 0; i < ND; ++i) {
+      v += (int64_t)x[i] * g.st[i];
+      v0 += (int64_t)blo[i] * g.st[i];
+      xs[i] = (float)x[i] * g.sw[i];
+    }
+    // unconditional loads (lanes outside the image read the block's corner)
+    const int64_t vl = valid ? v : v0;
+    float I[CM];
+    for (int c = 0; c < C; ++c) I[c] = (float)img[vl * C + c];
+
+    // --- gather: lane i <- the i-th record of the bins around the block ------
+    int b0[ND], b1[ND];
+    for (int i = 0; i < ND; ++i) {
+      b0[i] = max(blo[i] / g.S[i] - 1, 0);
+      b1[i] = min(bhi[i] / g.S[i] + 1, g.nb[i] - 1);
+    }
+    int jl = 0, cnt = 0;
+    {
+      int rc[ND];
+      for (int i = 1; i < ND; ++i) rc[i] = b0[i];
+      while (true) {
+        int bl = b0[0] * (int)g.bst[0];
+        for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
+        const int ja = a.bstart[bl];
+        const int jb = a.bstart[bl + (b1[0] - b0[0]) + 1];
+        if (lane >= cnt && lane < cnt + (jb - ja)) jl = ja + lane - cnt;
+        cnt += jb - ja;
+        int i = 1;
+        while (i < ND) {
+          if (++rc[i] <= b1[i]) break;
+          rc[i] = b0[i];
+          ++i;
+        }
+        if (i >= ND) break;
+      }
+    }
+    float best = __builtin_inff();
+    int bk = -1;
+    if (cnt <= 64) {
+      bool meets = false;
+      int flags = 0;
+      if (lane < cnt) {
+        const int* irec = reinterpret_cast<const int*>(a.brec + (int64_t)jl * RS);
+        meets = true;
+        for (int i = 0; i < ND; ++i) {
+          const int lo = irec[C + ND + i], hi = irec[C + 2 * ND + i];
+          meets = meets && lo <= bhi[i] && hi >= blo[i];
+          if (lo > blo[i] || hi < bhi[i]) flags |= 1 << i;
+        }
+      }
+      uint64_t mask = __ballot(meets);
+      int maxk = -1;
+      while (mask) {
+        const int l = (int)__builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int j = __builtin_amdgcn_readlane(jl, l);
+        const int fl = __builtin_amdgcn_readlane(flags, l);
+        const float* rec = a.brec + (int64_t)j * RS;
+        float R[RW];
+#pragma unroll
+        for (int w = 0; w < RW; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+        const int* Ri = reinterpret_cast<const int*>(R);
+        float D;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          const float d = xs[i] - R[C + i];
+          D = i == 0 ? d * d : fmaf(d, d, D);
+        }
+        for (int c = 0; c < C; ++c) {
+          const float t = I[c] - R[c];
+          D = fmaf(t, t, D);
+        }
+        if (fl) {
+          bool ok = true;
+#pragma unroll
+          for (int i = 0; i < ND; ++i)
+            if (fl & (1 << i)) ok &= (x[i] >= Ri[C + ND + i]) & (x[i] <= Ri[C + 2 * ND + i]);
+          D = ok ? D : __builtin_inff();
+        }
+        const int k = Ri[C + 3 * ND];
+        if (k > maxk) {
+          maxk = k;
+          if (D < best) {
+            best = D;
+            bk = k;
+          }
+        } else if (D < best || (D == best && k < bk && D != __builtin_inff())) {
+          best = D;
+          bk = k;
+        }
+      }
+    } else {
+      // more centres than lanes (a crowded neighbourhood): each lane walks them
+      int rc[ND];
+      for (int i = 1; i < ND; ++i) rc[i] = b0[i];
+      while (true) {
+        int bl = b0[0] * (int)g.bst[0];
+        for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
+        const int ja = a.bstart[bl];
+        const int jb = a.bstart[bl + (b1[0] - b0[0]) + 1];
+        for (int j = ja; j < jb; ++j) {
+          const float* rec = a.brec + (int64_t)j * RS;
+          const int* irec = reinterpret_cast<const int*>(rec);
+          bool ok = true;
+          for (int i = 0; i < ND; ++i) ok = ok && x[i] >= irec[C + ND + i] && x[i] <= irec[C + 2 * ND + i];
+          if (!ok) continue;
+          float D;
+          for (int i = 0; i < ND; ++i) {
+            const float d = xs[i] - rec[C + i];
+            D = i == 0 ? d * d : fmaf(d, d, D);
+          }
+          for (int c = 0; c < C; ++c) {
+            const float t = I[c] - rec[c];
+            D = fmaf(t, t, D);
+          }
+          const int k = irec[C + 3 * ND];
+          if (D < best || (D == best && k < bk)) {
+            best = D;
+            bk = k;
+          }
+        }
+        int i = 1;
+        while (i < ND) {
+          if (++rc[i] <= b1[i]) break;
+          rc[i] = b0[i];
+          ++i;
+        }
+        if (i >= ND) break;
+      }
+    }
+    if (valid) {
+      if (bk < 0) bk = a.first ? grid_label(g, x, ND) : a.labels[v];
+      a.labels[v] = bk;
+      if constexpr (ACC) {
+        if (bk != cur) {
+          flush();
+          cur = bk;
+          rcnt = 0;
+          for (int i = 0; i < ND; ++i) rco[i] = 0;
+          for (int c = 0; c < C; ++c) rch[c] = 0;
+        }
+        ++rcnt;
+        for (int i = 0; i < ND; ++i) rco[i] += (uint32_t)(x[i] - to[i]);
+        for (int c = 0; c < C; ++c) {
+          if constexpr (FLT) rch[c] += (double)I[c];
+          else rch[c] += (uint32_t)I[c];
+        }
+      }
+    }
+  }
+  if constexpr (!ACC) {
+    return;
+  } else {
+  flush();
+  __syncthreads();
+
+  // --- the tile's sums to their cluster slots -------------------------------
+  constexpr int NS = 1 << ND;
+  for (int s = tid; s < HS; s += kThreads) {
+    const int k = s_keys[s];
+    if (k < 0) continue;
+    const uint64_t* vv = s_vals + s * F;
+    const uint64_t n = vv[0];
+    uint64_t out[FM];
+    out[0] = n;
+    for (int i = 0; i < ND; ++i) out[1 + i] = vv[1 + i] + n * (uint64_t)to[i];
+    for (int c = 0; c < C; ++c) out[1 + ND + c] = vv[1 + ND + c];
+    int q = -1;
+    if (a.slots) {
+      const int* irec = reinterpret_cast<const int*>(a.ctab + (int64_t)k * g.rs);
+      q = 0;
+      for (int i = 0; i < ND; ++i) {
+        const int lo = max(irec[g.C + g.nd + i], 0), hi = min(irec[g.C + 2 * g.nd + i], g.n[i] - 1);
+        const int t0 = lo / SS::T[i];
+        const int d = tc[i] - t0;
+        const bool meets = to[i] <= hi && to[i] + SS::T[i] - 1 >= lo;
+        if (!meets || d < 0 || d > 1) {
+          q = -1;
+          break;
+        }
+        q |= d << i;
+      }
+    }
+    if (q >= 0) {
+      uint64_t* dst = a.part + ((int64_t)k * NS + q) * F;
+      for (int f = 0; f < F; ++f) dst[f] = out[f];
+    } else {
+      unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)k * F);
+      for (int f = 0; f < 1 + ND; ++f) atomicAdd(gg + f, (unsigned long long)out[f]);
+      for (int c = 0; c < C; ++c) {
+        if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(gg + 1 + ND + c), __longlong_as_double((long long)out[1 + ND + c]));
+        else atomicAdd(gg + 1 + ND + c, (unsigned long long)out[1 + ND + c]);
+      }
+    }
+  }
+  }
+}
+
+template <typename T, int ND, bool ACC>
+hipError_t dispatch_c(const Geo& g, const void* img, SweepArgs a, hipStream_t s) {
+  using SS = SweepShape<ND>;
+  int nt = 1;
+  a.slots = 1;
+  for (int i = 0; i < kMaxDim; ++i) a.nt[i] = 1;
+  for (int i = 0; i < ND; ++i) {
+    a.nt[i] = (g.n[i] + SS::T[i] - 1) / SS::T[i];
+    nt *= a.nt[i];
+    if (SS::T[i] < 2 * g.S[i] + 1) a.slots = 0;
+  }
+  a.ntiles = nt;
+  const unsigned grid = (unsigned)(((int64_t)nt + 7) / 8 * 8);  // a multiple of the XCD count
+  const T* p = (const T*)img;
+  switch (g.C) {
+    case 1: sweep_kernel<T, ND, 1, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
+    case 3: sweep_kernel<T, ND, 3, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
+    case 4: sweep_kernel<T, ND, 4, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
+    default: sweep_kernel<T, ND, 0, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, bool ACC>
+hipError_t dispatch_nd(const Geo& g, const void* img, const SweepArgs& a, hipStream_t s) {
+  switch (g.nd) {
+    case 2: return dispatch_c<T, 2, ACC>(g, img, a, s);
+    case 3: return dispatch_c<T, 3, ACC>(g, img, a, s);
+    default: return dispatch_c<T, 4, ACC>(g, img, a, s);
+  }
+}
+
+template <bool ACC>
+hipError_t dispatch(const Geo& g, const void* img, const SweepArgs& a, hipStream_t s) {
+  switch (g.dtype) {
+    case kU8: return dispatch_nd<uint8_t, ACC>(g, img, a, s);
+    case kU16: return dispatch_nd<uint16_t, ACC>(g, img, a, s);
+    default: return dispatch_nd<float, ACC>(g, img, a, s);
+  }
+}
+
+}  // namespace
+
+int sweep_slots(const Geo& g) {
+  for (int i = 0; i < g.nd; ++i) {
+    int T = g.nd == 2 ? SweepShape<2>::T[i] : g.nd == 3 ? SweepShape<3>::T[i] : SweepShape<4>::T[i];
+    if (T < 2 * g.S[i] + 1) return 0;
+  }
+  return 1;
+}
+
+void sweep_tile_shape(int nd, int* T) {
+  for (int i = 0; i < nd; ++i)
+    T[i] = nd == 2 ? SweepShape<2>::T[i] : nd == 3 ? SweepShape<3>::T[i] : SweepShape<4>::T[i];
+}
+
+hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels, int first,
+                        int accumulate, hipStream_t s) {
+  SweepArgs a{};
+  a.bstart = it.bin_start;
+  a.brec = it.brec;
+  a.ctab = it.ctab;
+  a.labels = labels;
+  a.first = first;
+  a.done = it.done;
+  a.part = it.part;
+  a.acc = it.acc;
+  return accumulate ? dispatch<true>(g, img, a, s) : dispatch<false>(g, img, a, s);
+}
+
+}  // namespace sslic

@@ -99,11 +99,32 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
   };
 
   if (x < n0) {
+    // load the column's labels and values first, so the reads are in flight together
+    using VT = typename std::conditional<FLT, float, uint32_t>::type;
+    const int nr = (int)min((int64_t)kRowsPerWave, nrows - r0);
+    int lab[kRowsPerWave];
+    VT val[kRowsPerWave][CC > 0 ? CC : kMaxChan];
+#pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
-      int64_t r = r0 + j;
-      if (r >= nrows) break;
-      int64_t v = r * n0 + x;
-      int l = labels[v];
+      lab[j] = -1;
+      if (j < nr) {
+        const int64_t v = (r0 + j) * n0 + x;
+        lab[j] = labels[v];
+        for (int c = 0; c < C; ++c) val[j][c] = (VT)img[v * C + c];
+      }
+    }
+    int y[ND];  // coordinates of row r0 (axes 1..), advanced with carries
+    {
+      int64_t rr = r0;
+      for (int i = 1; i < ND; ++i) {
+        y[i] = (int)(rr % g.n[i]);
+        rr /= g.n[i];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsPerWave; ++j) {
+      if (j >= nr) continue;  // (no break: the loop must unroll to keep lab/val in registers)
+      const int l = lab[j];
       if (l != cur) {
         flush();
         cur = l;
@@ -113,12 +134,12 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
       }
       ++cnt;
       sc[0] += (uint64_t)x;
-      int64_t rr = r;
+      for (int i = 1; i < ND; ++i) sc[i] += (uint64_t)y[i];
+      for (int c = 0; c < C; ++c) sch[c] += (CS)val[j][c];
       for (int i = 1; i < ND; ++i) {
-        sc[i] += (uint64_t)(rr % g.n[i]);
-        rr /= g.n[i];
+        if (++y[i] < g.n[i]) break;
+        y[i] = 0;
       }
-      for (int c = 0; c < C; ++c) sch[c] += (CS)img[v * C + c];
     }
     flush();
   }
