@@ -268,3 +268,24 @@ def test_run_init_centres_resume(ctx):
                      init_centres=f32_exact(a["centres"]))
     agree = float((host(got["labels"]) == exp["labels"]).mean())
     assert agree >= 0.999
+
+
+def test_assign_crowded_tile_and_uncovered_voxels(ctx):
+    """600 centres packed into a 30x30 patch: tiles near it hold more centres
+    than fit in LDS and take the per-voxel path; voxels far from every window
+    keep their previous label."""
+    rng = np.random.default_rng(8)
+    img = rand_image((200, 150), 3, np.uint8, 5)
+    K = 600
+    cen = np.zeros((K, 5))
+    cen[:, :3] = rng.uniform(0, 255, (K, 3))
+    cen[:, 3:] = rng.uniform(40, 70, (K, 2))
+    cen = f32_exact(cen)
+    prev = rng.integers(0, K, 200 * 150).astype(np.int32)
+    exp = prev.copy()
+    oracle.assign(img, 2, (16, 16), 10.0, cen, exp)
+    got = dev(prev)
+    ctx.assign(dev(img), (16, 16), 10.0, dev(cen), got)
+    got = host(got)
+    assert (exp == prev).mean() > 0.5  # most voxels are out of every window
+    assert float((got != exp).mean()) <= ASSIGN_TOL
