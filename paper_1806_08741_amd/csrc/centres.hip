@@ -297,47 +297,60 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
-__global__ void finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts,
-                                Iter it, int t, int prep_next, int use_part, TileDims td) {
+template <int ND, int CC, bool FLT>
+__global__ void __launch_bounds__(kThreads)
+finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, Iter it, int t,
+                int prep_next, int use_part, TileDims td) {
   if (*it.done) return;
+  constexpr int CM = CC > 0 ? CC : kMaxChan;
+  const int C = CC > 0 ? CC : g.C;
+  const int F = 1 + ND + C;
   __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double e_sum = 0.0, e_cnt = 0.0;
   if (k < g.K) {
-    const bool flt = g.dtype == kF32;
-    uint64_t* a = it.acc + k * g.F;
-    uint64_t si[1 + kMaxDim + kMaxChan];
-    double sf[kMaxChan];
-    for (int f = 0; f < g.F; ++f) {
-      si[f] = a[f];
-      a[f] = 0;
+    uint64_t* a = it.acc + k * F;
+    uint64_t si[1 + ND];
+    uint64_t sc[CM];
+    double sf[CM];
+#pragma unroll
+    for (int f = 0; f < 1 + ND; ++f) si[f] = a[f];
+    for (int c = 0; c < C; ++c) {
+      sc[c] = a[1 + ND + c];
+      sf[c] = __longlong_as_double((long long)sc[c]);
     }
-    for (int c = 0; c < g.C; ++c) sf[c] = __longlong_as_double((long long)si[1 + g.nd + c]);
+    for (int f = 0; f < F; ++f) a[f] = 0;
     if (use_part) {
       // the slots of the tiles this cluster's window meets (as the sweep chose them)
       const int32_t* irec = reinterpret_cast<const int32_t*>(it.ctab + k * g.rs);
-      int lo[kMaxDim], hi[kMaxDim], t0[kMaxDim];
-      for (int i = 0; i < g.nd; ++i) {
-        lo[i] = max(irec[g.C + g.nd + i], 0);
-        hi[i] = min(irec[g.C + 2 * g.nd + i], g.n[i] - 1);
+      int lo[ND], hi[ND], t0[ND];
+      bool any = true;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        lo[i] = max(irec[C + ND + i], 0);
+        hi[i] = min(irec[C + 2 * ND + i], g.n[i] - 1);
+        any = any && lo[i] <= hi[i];
         t0[i] = lo[i] / td.T[i];
       }
-      const int ns = 1 << g.nd;
-      for (int q = 0; q < ns; ++q) {
-        bool meets = true;
-        for (int i = 0; i < g.nd; ++i) {
-          const int tlo = (t0[i] + ((q >> i) & 1)) * td.T[i];
-          meets = meets && lo[i] <= hi[i] && tlo <= hi[i] && tlo + td.T[i] - 1 >= lo[i];
+      if (any) {
+#pragma unroll
+        for (int q = 0; q < (1 << ND); ++q) {
+          bool meets = true;
+#pragma unroll
+          for (int i = 0; i < ND; ++i) {
+            if ((q >> i) & 1) meets = meets && (t0[i] + 1) * td.T[i] <= hi[i];
+          }
+          if (!meets) continue;
+          uint64_t* p = it.part + (k * (1 << ND) + q) * F;
+#pragma unroll
+          for (int f = 0; f < 1 + ND; ++f) si[f] += p[f];
+          for (int c = 0; c < C; ++c) {
+            const uint64_t raw = p[1 + ND + c];
+            if (FLT) sf[c] += __longlong_as_double((long long)raw);
+            else sc[c] += raw;
+          }
+          for (int f = 0; f < F; ++f) p[f] = 0;
         }
-        if (!meets) continue;
-        uint64_t* p = it.part + (k * ns + q) * g.F;
-        for (int f = 0; f < 1 + g.nd; ++f) si[f] += p[f];
-        for (int c = 0; c < g.C; ++c) {
-          const uint64_t raw = p[1 + g.nd + c];
-          if (flt) sf[c] += __longlong_as_double((long long)raw);
-          else si[1 + g.nd + c] += raw;
-        }
-        for (int f = 0; f < g.F; ++f) p[f] = 0;
       }
     }
     const uint64_t n = si[0];
@@ -345,17 +358,17 @@ __global__ void finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __rest
     if (n > 0) {
       double dn = (double)n;
       double e = 0.0;
-      for (int c = 0; c < g.C; ++c) {
-        double nv = flt ? sf[c] / dn : (double)si[1 + g.nd + c] / dn;
+      for (int c = 0; c < C; ++c) {
+        double nv = FLT ? sf[c] / dn : (double)sc[c] / dn;
         double d = nv - row[c];
         e = e + d * d;
         row[c] = nv;
       }
       for (int i = 0; i < g.nd_out; ++i) {
         double nv = (double)si[1 + i] / dn;
-        double d = nv - row[g.C + i];
+        double d = nv - row[C + i];
         e = e + g.wd[i] * (d * d);
-        row[g.C + i] = nv;
+        row[C + i] = nv;
       }
       e_sum = sqrt(e);
       e_cnt = 1.0;
@@ -435,8 +448,27 @@ hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Ite
                            int prep_next, int use_part, hipStream_t s) {
   TileDims td{};
   sweep_tile_shape(g.nd, td.T);
-  finalize_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, counts, it, t, prep_next,
-                                                       use_part, td);
+  const unsigned nb = blocks_for(g.K);
+  const bool flt = g.dtype == kF32;
+#define SSLIC_FIN(ND, CC)                                                                     \
+  (flt ? (finalize_kernel<ND, CC, true><<<nb, kThreads, 0, s>>>(g, cen, counts, it, t, prep_next, \
+                                                               use_part, td), 0)              \
+       : (finalize_kernel<ND, CC, false><<<nb, kThreads, 0, s>>>(g, cen, counts, it, t,       \
+                                                                prep_next, use_part, td), 0))
+#define SSLIC_FIN_C(ND)                       \
+  switch (g.C) {                              \
+    case 1: SSLIC_FIN(ND, 1); break;          \
+    case 3: SSLIC_FIN(ND, 3); break;          \
+    case 4: SSLIC_FIN(ND, 4); break;          \
+    default: SSLIC_FIN(ND, 0); break;         \
+  }
+  switch (g.nd) {
+    case 2: SSLIC_FIN_C(2); break;
+    case 3: SSLIC_FIN_C(3); break;
+    default: SSLIC_FIN_C(4); break;
+  }
+#undef SSLIC_FIN_C
+#undef SSLIC_FIN
   return hipGetLastError();
 }
 

@@ -85,14 +85,15 @@ struct RunSum<true> {
 
 template <typename T, int ND, int CC, bool ACC>
 __global__ void __launch_bounds__(kThreads)
-sweep_kernel(Geo g, const T* __restrict__ img, SweepArgs a) {
+sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
+             const float* __restrict__ brec, SweepArgs a) {
   if (*a.done) return;
   using SS = SweepShape<ND>;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   constexpr int RW = (CM + 3 * ND + 1 + 3) & ~3;
+  constexpr int RN = CM + 3 * ND + 1;  // record words read
   constexpr int HS = SS::kHash;
   constexpr int FM = 1 + ND + CM;
-  constexpr int NBW = blocks_per_tile<ND>() / kWaves;
   constexpr bool FLT = std::is_same<T, float>::value;
   using RT = typename RunSum<FLT>::type;
   const int C = CC > 0 ? CC : g.C;
@@ -173,171 +174,259 @@ sweep_kernel(Geo g, const T* __restrict__ img, SweepArgs a) {
     }
   };
 
-  for (int q = 0; q < NBW; ++q) {
-    // block origin (global) and extent
-    int blo[ND], bhi[ND], x[ND];
-    bool inside = true, valid = true;
-    {
-      int r = wave * NBW + q;
-      for (int i = 0; i < ND; ++i) {
-        const int nbk = SS::T[i] / SS::B[i];
-        blo[i] = to[i] + (r % nbk) * SS::B[i];
-        r /= nbk;
-        inside = inside && blo[i] < g.n[i];
-        bhi[i] = min(blo[i] + SS::B[i], g.n[i]) - 1;
-        x[i] = blo[i] + lx[i];
-        valid = valid && x[i] <= bhi[i];
+  // Lane-parallel gather: lane i <- position of the i-th record in the bins
+  // b0..b1 (rows of bins along axis 0 are contiguous in the record array).
+  auto gather = [&](const int* b0, const int* b1, int& jl) {
+    int cnt = 0;
+    int rc[ND];
+    for (int i = 1; i < ND; ++i) rc[i] = b0[i];
+    while (true) {
+      int bl = b0[0] * (int)g.bst[0];
+      for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
+      const int ja = bstart[bl];
+      const int jb = bstart[bl + (b1[0] - b0[0]) + 1];
+      if (lane >= cnt && lane < cnt + (jb - ja)) jl = ja + lane - cnt;
+      cnt += jb - ja;
+      int i = 1;
+      while (i < ND) {
+        if (++rc[i] <= b1[i]) break;
+        rc[i] = b0[i];
+        ++i;
       }
+      if (i >= ND) break;
     }
-    if (!inside) continue;
-    int64_t v = 0, v0 = 0;
-    float xs[ND];
-    for (int i = 0; i < ND; ++i) {
-      v += (int64_t)x[i] * g.st[i];
-      v0 += (int64_t)blo[i] * g.st[i];
-      xs[i] = (float)x[i] * g.sw[i];
-    }
-    // unconditional loads (lanes outside the image read the block's corner)
-    const int64_t vl = valid ? v : v0;
-    float I[CM];
-    for (int c = 0; c < C; ++c) I[c] = (float)img[vl * C + c];
+    return cnt;
+  };
 
-    // --- gather: lane i <- the i-th record of the bins around the block ------
-    int b0[ND], b1[ND];
-    for (int i = 0; i < ND; ++i) {
-      b0[i] = max(blo[i] / g.S[i] - 1, 0);
-      b1[i] = min(bhi[i] / g.S[i] + 1, g.nb[i] - 1);
-    }
-    int jl = 0, cnt = 0;
-    {
-      int rc[ND];
-      for (int i = 1; i < ND; ++i) rc[i] = b0[i];
-      while (true) {
-        int bl = b0[0] * (int)g.bst[0];
-        for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
-        const int ja = a.bstart[bl];
-        const int jb = a.bstart[bl + (b1[0] - b0[0]) + 1];
-        if (lane >= cnt && lane < cnt + (jb - ja)) jl = ja + lane - cnt;
-        cnt += jb - ja;
-        int i = 1;
-        while (i < ND) {
-          if (++rc[i] <= b1[i]) break;
-          rc[i] = b0[i];
-          ++i;
-        }
-        if (i >= ND) break;
-      }
-    }
-    float best = __builtin_inff();
-    int bk = -1;
-    if (cnt <= 64) {
-      bool meets = false;
-      int flags = 0;
-      if (lane < cnt) {
-        const int* irec = reinterpret_cast<const int*>(a.brec + (int64_t)jl * RS);
-        meets = true;
-        for (int i = 0; i < ND; ++i) {
-          const int lo = irec[C + ND + i], hi = irec[C + 2 * ND + i];
-          meets = meets && lo <= bhi[i] && hi >= blo[i];
-          if (lo > blo[i] || hi < bhi[i]) flags |= 1 << i;
-        }
-      }
-      uint64_t mask = __ballot(meets);
-      int maxk = -1;
-      while (mask) {
-        const int l = (int)__builtin_ctzll(mask);
-        mask &= mask - 1;
-        const int j = __builtin_amdgcn_readlane(jl, l);
-        const int fl = __builtin_amdgcn_readlane(flags, l);
-        const float* rec = a.brec + (int64_t)j * RS;
-        float R[RW];
+  // The meeting centres of a block, one at a time: batches of UB records are
+  // read with scalar loads issued back to back, then each updates (best, bk).
+  auto scan = [&](uint64_t mask, int jo, int flags, const int* x, const float* xs, const float* I,
+                  float& best, int& bk) {
+    constexpr int UB = CC > 0 ? 4 : 2;
+    while (mask) {
+      int co[UB], cf[UB];
+      bool cv[UB];
 #pragma unroll
-        for (int w = 0; w < RW; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
-        const int* Ri = reinterpret_cast<const int*>(R);
+      for (int u = 0; u < UB; ++u) {
+        cv[u] = mask != 0;
+        const int l = cv[u] ? (int)__builtin_ctzll(mask) : 0;
+        co[u] = __builtin_amdgcn_readlane(jo, l);
+        cf[u] = cv[u] ? __builtin_amdgcn_readlane(flags, l) : 0;
+        mask &= mask - 1;
+      }
+      float R[UB][RN];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + co[u]);
+#pragma unroll
+        for (int w = 0; w < RN; ++w) R[u][w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (!cv[u]) break;
+        const int* Ri = reinterpret_cast<const int*>(R[u]);
         float D;
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
-          const float d = xs[i] - R[C + i];
+          const float d = xs[i] - R[u][C + i];
           D = i == 0 ? d * d : fmaf(d, d, D);
         }
         for (int c = 0; c < C; ++c) {
-          const float t = I[c] - R[c];
+          const float t = I[c] - R[u][c];
           D = fmaf(t, t, D);
         }
-        if (fl) {
+        const int fl = cf[u];
+        if (fl) {  // only the window sides that fall inside the block are tested
           bool ok = true;
 #pragma unroll
-          for (int i = 0; i < ND; ++i)
-            if (fl & (1 << i)) ok &= (x[i] >= Ri[C + ND + i]) & (x[i] <= Ri[C + 2 * ND + i]);
+          for (int i = 0; i < ND; ++i) {
+            if (fl & (1 << (2 * i))) ok &= x[i] >= Ri[C + ND + i];
+            if (fl & (2 << (2 * i))) ok &= x[i] <= Ri[C + 2 * ND + i];
+          }
           D = ok ? D : __builtin_inff();
         }
         const int k = Ri[C + 3 * ND];
-        if (k > maxk) {
-          maxk = k;
-          if (D < best) {
-            best = D;
-            bk = k;
-          }
-        } else if (D < best || (D == best && k < bk && D != __builtin_inff())) {
-          best = D;
-          bk = k;
-        }
-      }
-    } else {
-      // more centres than lanes (a crowded neighbourhood): each lane walks them
-      int rc[ND];
-      for (int i = 1; i < ND; ++i) rc[i] = b0[i];
-      while (true) {
-        int bl = b0[0] * (int)g.bst[0];
-        for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
-        const int ja = a.bstart[bl];
-        const int jb = a.bstart[bl + (b1[0] - b0[0]) + 1];
-        for (int j = ja; j < jb; ++j) {
-          const float* rec = a.brec + (int64_t)j * RS;
-          const int* irec = reinterpret_cast<const int*>(rec);
-          bool ok = true;
-          for (int i = 0; i < ND; ++i) ok = ok && x[i] >= irec[C + ND + i] && x[i] <= irec[C + 2 * ND + i];
-          if (!ok) continue;
-          float D;
-          for (int i = 0; i < ND; ++i) {
-            const float d = xs[i] - rec[C + i];
-            D = i == 0 ? d * d : fmaf(d, d, D);
-          }
-          for (int c = 0; c < C; ++c) {
-            const float t = I[c] - rec[c];
-            D = fmaf(t, t, D);
-          }
-          const int k = irec[C + 3 * ND];
+        // best starts at FLT_MAX, so only real distances can tie; ties are
+        // rare and only then is the cluster index compared
+        if (__ballot(D == best)) {
           if (D < best || (D == best && k < bk)) {
             best = D;
             bk = k;
           }
+        } else if (D < best) {
+          best = D;
+          bk = k;
         }
-        int i = 1;
-        while (i < ND) {
-          if (++rc[i] <= b1[i]) break;
-          rc[i] = b0[i];
-          ++i;
-        }
-        if (i >= ND) break;
       }
     }
-    if (valid) {
-      if (bk < 0) bk = a.first ? grid_label(g, x, ND) : a.labels[v];
-      a.labels[v] = bk;
-      if constexpr (ACC) {
-        if (bk != cur) {
-          flush();
-          cur = bk;
-          rcnt = 0;
-          for (int i = 0; i < ND; ++i) rco[i] = 0;
-          for (int c = 0; c < C; ++c) rch[c] = 0;
+  };
+
+  // meets / cut sides of the record held by this lane against a block box
+  auto test = [&](bool held, const int* lo, const int* hi, const int* blo, const int* bhi,
+                  int& flags) {
+    bool meets = held;
+    flags = 0;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      meets = meets && lo[i] <= bhi[i] && hi[i] >= blo[i];
+      if (lo[i] > blo[i]) flags |= 1 << (2 * i);
+      if (hi[i] < bhi[i]) flags |= 2 << (2 * i);
+    }
+    return meets;
+  };
+
+  constexpr int BX = SS::T[0] / SS::B[0];            // blocks per row (axis 0)
+  constexpr int NROW = blocks_per_tile<ND>() / BX;   // block rows per tile
+  static_assert(NROW % kWaves == 0, "rows must split evenly over waves");
+  constexpr int RPW = NROW / kWaves;
+
+  for (int rw = 0; rw < RPW; ++rw) {
+    // a row of blocks along axis 0 across the tile
+    int rlo[ND], rhi[ND];
+    bool rin = true;
+    {
+      int r = wave * RPW + rw;
+      rlo[0] = to[0];
+      rhi[0] = min(to[0] + SS::T[0], g.n[0]) - 1;
+      for (int i = 1; i < ND; ++i) {
+        const int nbk = SS::T[i] / SS::B[i];
+        rlo[i] = to[i] + (r % nbk) * SS::B[i];
+        r /= nbk;
+        rin = rin && rlo[i] < g.n[i];
+        rhi[i] = min(rlo[i] + SS::B[i], g.n[i]) - 1;
+      }
+    }
+    if (!rin) continue;
+    // the records of the bins within one bin of the row, one per lane
+    int rb0[ND], rb1[ND];
+    for (int i = 0; i < ND; ++i) {
+      rb0[i] = max(rlo[i] / g.S[i] - 1, 0);
+      rb1[i] = min(rhi[i] / g.S[i] + 1, g.nb[i] - 1);
+    }
+    int rjl = 0;
+    const int nrec = gather(rb0, rb1, rjl);
+    const bool rowfit = nrec <= 64;
+    const bool held = rowfit && lane < nrec;
+    int hlo[ND], hhi[ND];
+    const int hjo = rjl * RS * 4;
+    {
+      const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(held ? rjl : 0) * RS);
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        hlo[i] = irec[C + ND + i];
+        hhi[i] = irec[C + 2 * ND + i];
+      }
+    }
+
+    for (int bx = 0; bx < BX; ++bx) {
+      int blo[ND], bhi[ND], x[ND];
+      bool valid = true;
+      blo[0] = to[0] + bx * SS::B[0];
+      if (blo[0] >= g.n[0]) break;
+      bhi[0] = min(blo[0] + SS::B[0], g.n[0]) - 1;
+      for (int i = 1; i < ND; ++i) {
+        blo[i] = rlo[i];
+        bhi[i] = rhi[i];
+      }
+      for (int i = 0; i < ND; ++i) {
+        x[i] = blo[i] + lx[i];
+        valid = valid && x[i] <= bhi[i];
+      }
+      int64_t v = 0, v0 = 0;
+      float xs[ND];
+      for (int i = 0; i < ND; ++i) {
+        v += (int64_t)x[i] * g.st[i];
+        v0 += (int64_t)blo[i] * g.st[i];
+        xs[i] = (float)x[i] * g.sw[i];
+      }
+      // unconditional loads (lanes outside the image read the block's corner)
+      const int64_t vl = valid ? v : v0;
+      float I[CM];
+      for (int c = 0; c < C; ++c) I[c] = (float)img[vl * C + c];
+
+      float best = 3.402823466e38f;  // FLT_MAX: out-of-window distances (+inf) never win or tie
+      int bk = -1;
+      if (rowfit) {
+        int flags;
+        const bool meets = test(held, hlo, hhi, blo, bhi, flags);
+        scan(__ballot(meets), hjo, flags, x, xs, I, best, bk);
+      } else {
+        int b0[ND], b1[ND];
+        for (int i = 0; i < ND; ++i) {
+          b0[i] = max(blo[i] / g.S[i] - 1, 0);
+          b1[i] = min(bhi[i] / g.S[i] + 1, g.nb[i] - 1);
         }
-        ++rcnt;
-        for (int i = 0; i < ND; ++i) rco[i] += (uint32_t)(x[i] - to[i]);
-        for (int c = 0; c < C; ++c) {
-          if constexpr (FLT) rch[c] += (double)I[c];
-          else rch[c] += (uint32_t)I[c];
+        int jl = 0;
+        const int cnt = gather(b0, b1, jl);
+        if (cnt <= 64) {
+          const bool bheld = lane < cnt;
+          int lo[ND], hi[ND];
+          const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(bheld ? jl : 0) * RS);
+          for (int i = 0; i < ND; ++i) {
+            lo[i] = irec[C + ND + i];
+            hi[i] = irec[C + 2 * ND + i];
+          }
+          int flags;
+          const bool meets = test(bheld, lo, hi, blo, bhi, flags);
+          scan(__ballot(meets), jl * RS * 4, flags, x, xs, I, best, bk);
+        } else {
+          // more centres than lanes (a crowded neighbourhood): each lane walks them
+          int rc[ND];
+          for (int i = 1; i < ND; ++i) rc[i] = b0[i];
+          while (true) {
+            int bl = b0[0] * (int)g.bst[0];
+            for (int i = 1; i < ND; ++i) bl += rc[i] * (int)g.bst[i];
+            const int ja = bstart[bl];
+            const int jb = bstart[bl + (b1[0] - b0[0]) + 1];
+            for (int j = ja; j < jb; ++j) {
+              const float* rec = brec + (int64_t)j * RS;
+              const int* irec2 = reinterpret_cast<const int*>(rec);
+              bool ok = true;
+              for (int i = 0; i < ND; ++i)
+                ok = ok && x[i] >= irec2[C + ND + i] && x[i] <= irec2[C + 2 * ND + i];
+              if (!ok) continue;
+              float D;
+              for (int i = 0; i < ND; ++i) {
+                const float d = xs[i] - rec[C + i];
+                D = i == 0 ? d * d : fmaf(d, d, D);
+              }
+              for (int c = 0; c < C; ++c) {
+                const float t = I[c] - rec[c];
+                D = fmaf(t, t, D);
+              }
+              const int k = irec2[C + 3 * ND];
+              if (D < best || (D == best && k < bk)) {
+                best = D;
+                bk = k;
+              }
+            }
+            int i = 1;
+            while (i < ND) {
+              if (++rc[i] <= b1[i]) break;
+              rc[i] = b0[i];
+              ++i;
+            }
+            if (i >= ND) break;
+          }
+        }
+      }
+      if (valid) {
+        if (bk < 0) bk = a.first ? grid_label(g, x, ND) : a.labels[v];
+        a.labels[v] = bk;
+        if constexpr (ACC) {
+          if (bk != cur) {
+            flush();
+            cur = bk;
+            rcnt = 0;
+            for (int i = 0; i < ND; ++i) rco[i] = 0;
+            for (int c = 0; c < C; ++c) rch[c] = 0;
+          }
+          ++rcnt;
+          for (int i = 0; i < ND; ++i) rco[i] += (uint32_t)(x[i] - to[i]);
+          for (int c = 0; c < C; ++c) {
+            if constexpr (FLT) rch[c] += (double)I[c];
+            else rch[c] += (uint32_t)I[c];
+          }
         }
       }
     }
@@ -405,10 +494,10 @@ hipError_t dispatch_c(const Geo& g, const void* img, SweepArgs a, hipStream_t s)
   const unsigned grid = (unsigned)(((int64_t)nt + 7) / 8 * 8);  // a multiple of the XCD count
   const T* p = (const T*)img;
   switch (g.C) {
-    case 1: sweep_kernel<T, ND, 1, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
-    case 3: sweep_kernel<T, ND, 3, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
-    case 4: sweep_kernel<T, ND, 4, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
-    default: sweep_kernel<T, ND, 0, ACC><<<grid, kThreads, 0, s>>>(g, p, a); break;
+    case 1: sweep_kernel<T, ND, 1, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
+    case 3: sweep_kernel<T, ND, 3, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
+    case 4: sweep_kernel<T, ND, 4, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
+    default: sweep_kernel<T, ND, 0, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
   }
   return hipGetLastError();
 }
