@@ -161,13 +161,13 @@ __device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_
       lo = 1073741824;
       hi = -1073741824;
     }
-    irec[g.C + g.nd + i] = lo;
-    irec[g.C + 2 * g.nd + i] = hi;
+    irec[rec_lo(g.C, g.nd) + i] = lo;
+    irec[rec_hi(g.C, g.nd) + i] = hi;
     int b = floordiv(lo, g.S[i]) + 1;
     b = min(max(b, 0), g.nb[i] - 1);
     bin += b * g.bst[i];
   }
-  irec[g.C + 3 * g.nd] = (int32_t)k;
+  irec[rec_k(g.C, g.nd)] = (int32_t)k;
   it.bin_of[k] = (int32_t)bin;
   atomicAdd(&it.bin_cnt[bin], 1);
 }
@@ -327,8 +327,8 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
       bool any = true;
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
-        lo[i] = max(irec[C + ND + i], 0);
-        hi[i] = min(irec[C + 2 * ND + i], g.n[i] - 1);
+        lo[i] = max(irec[rec_lo(C, ND) + i], 0);
+        hi[i] = min(irec[rec_hi(C, ND) + i], g.n[i] - 1);
         any = any && lo[i] <= hi[i];
         t0[i] = lo[i] / td.T[i];
       }

@@ -43,12 +43,16 @@ struct Geo {
 // Record k of the assignment centre table (FP32 words, stride g.rs):
 //   [0, C)            channel means mu_c
 //   [C, C+nd)         scaled coordinates c'_i = c_i * m / S_i (rounded from FP64)
-//   [C+nd, C+2nd)     int32 lo_i = ceil(c_i - S_i)   (FP64, clamped)
-//   [C+2nd, C+3nd)    int32 hi_i = floor(c_i + S_i)
-//   [C+3nd]           int32 cluster index k
+//   [C+nd]            int32 cluster index k
+//   [C+nd+1, C+2nd+1) int32 lo_i = ceil(c_i - S_i)   (FP64, clamped)
+//   [C+2nd+1, C+3nd+1) int32 hi_i = floor(c_i + S_i)
 // so that x is inside the closed window of k iff lo_i <= x_i <= hi_i, and
-// D^2(x, k) = sum_i (x_i * m / S_i - c'_i)^2 + sum_c (I_c(x) - mu_c)^2.
+// D^2(x, k) = sum_i (x_i * m / S_i - c'_i)^2 + sum_c (I_c(x) - mu_c)^2.  The
+// words a distance needs (mu, c', k) come first and contiguous.
 __host__ __device__ inline int rec_words(int C, int nd) { return (C + 3 * nd + 1 + 3) & ~3; }
+__host__ __device__ constexpr int rec_k(int C, int nd) { return C + nd; }
+__host__ __device__ constexpr int rec_lo(int C, int nd) { return C + nd + 1; }
+__host__ __device__ constexpr int rec_hi(int C, int nd) { return C + 2 * nd + 1; }
 
 // Device buffers used by one iteration loop.
 struct Iter {

@@ -198,81 +198,84 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
     return cnt;
   };
 
-  // The meeting centres of a block, one at a time: batches of UB records are
-  // read with scalar loads issued back to back, then each updates (best, bk).
-  auto scan = [&](uint64_t mask, int jo, int flags, const int* x, const float* xs, const float* I,
-                  float& best, int& bk) {
-    constexpr int UB = CC > 0 ? 4 : 2;
-    while (mask) {
-      int co[UB], cf[UB];
-      bool cv[UB];
+  // keeps the smaller (D, k) pair: the lowest cluster index among equal
+  // distances; best starts at FLT_MAX, so +inf (outside the window) never wins
+  auto pick = [&](float D, int k, float& best, int& bk) {
+    const bool lt = (D < best) | ((D == best) & (k < bk));  // bitwise: no branches
+    best = lt ? D : best;
+    bk = lt ? k : bk;
+  };
+
+  // The meeting centres of a block, one at a time (their records are scalar
+  // loads at byte offset readlane(jo, l)).  Centres whose window covers the
+  // whole block (mask mf) need no window test; for the others (mask mc) the
+  // closed window is tested on every axis as one unsigned range compare.
+  auto scan = [&](uint64_t mf, uint64_t mc, int jo, const int* x, const float* xs,
+                  const float* I, float& best, int& bk) {
+    constexpr int RF = CM + ND + 1;  // mu, c', k
+    while (mf) {
+      const int l = (int)__builtin_ctzll(mf);
+      mf &= mf - 1;
+      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
+      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + o);
+      float R[RF];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        cv[u] = mask != 0;
-        const int l = cv[u] ? (int)__builtin_ctzll(mask) : 0;
-        co[u] = __builtin_amdgcn_readlane(jo, l);
-        cf[u] = cv[u] ? __builtin_amdgcn_readlane(flags, l) : 0;
-        mask &= mask - 1;
+      for (int w = 0; w < RF; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+      float D;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const float d = xs[i] - R[C + i];
+        D = i == 0 ? d * d : fmaf(d, d, D);
       }
-      float R[UB][RN];
-#pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + co[u]);
-#pragma unroll
-        for (int w = 0; w < RN; ++w) R[u][w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+      for (int c = 0; c < C; ++c) {
+        const float t = I[c] - R[c];
+        D = fmaf(t, t, D);
       }
+      const int k = CC > 0 ? __float_as_int(R[rec_k(CC, ND)])
+                           : reinterpret_cast<const int*>(rec)[rec_k(C, ND)];
+      pick(D, k, best, bk);
+    }
+    while (mc) {
+      const int l = (int)__builtin_ctzll(mc);
+      mc &= mc - 1;
+      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
+      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + o);
+      float R[RN];
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        if (!cv[u]) break;
-        const int* Ri = reinterpret_cast<const int*>(R[u]);
-        float D;
+      for (int w = 0; w < RN; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+      const int* Ri = reinterpret_cast<const int*>(R);
+      float D;
 #pragma unroll
-        for (int i = 0; i < ND; ++i) {
-          const float d = xs[i] - R[u][C + i];
-          D = i == 0 ? d * d : fmaf(d, d, D);
-        }
-        for (int c = 0; c < C; ++c) {
-          const float t = I[c] - R[u][c];
-          D = fmaf(t, t, D);
-        }
-        const int fl = cf[u];
-        if (fl) {  // only the window sides that fall inside the block are tested
-          bool ok = true;
-#pragma unroll
-          for (int i = 0; i < ND; ++i) {
-            if (fl & (1 << (2 * i))) ok &= x[i] >= Ri[C + ND + i];
-            if (fl & (2 << (2 * i))) ok &= x[i] <= Ri[C + 2 * ND + i];
-          }
-          D = ok ? D : __builtin_inff();
-        }
-        const int k = Ri[C + 3 * ND];
-        // best starts at FLT_MAX, so only real distances can tie; ties are
-        // rare and only then is the cluster index compared
-        if (__ballot(D == best)) {
-          if (D < best || (D == best && k < bk)) {
-            best = D;
-            bk = k;
-          }
-        } else if (D < best) {
-          best = D;
-          bk = k;
-        }
+      for (int i = 0; i < ND; ++i) {
+        const float d = xs[i] - R[C + i];
+        D = i == 0 ? d * d : fmaf(d, d, D);
       }
+      for (int c = 0; c < C; ++c) {
+        const float t = I[c] - R[c];
+        D = fmaf(t, t, D);
+      }
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const int lo = Ri[rec_lo(C, ND) + i], hi = Ri[rec_hi(C, ND) + i];
+        ok &= (uint32_t)(x[i] - lo) <= (uint32_t)(hi - lo);
+      }
+      D = ok ? D : __builtin_inff();
+      pick(D, Ri[rec_k(C, ND)], best, bk);
     }
   };
 
-  // meets / cut sides of the record held by this lane against a block box
+  // meets / covers test of the record held by this lane against a block box
   auto test = [&](bool held, const int* lo, const int* hi, const int* blo, const int* bhi,
-                  int& flags) {
-    bool meets = held;
-    flags = 0;
+                  uint64_t& mf, uint64_t& mc) {
+    bool meets = held, covers = true;
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       meets = meets && lo[i] <= bhi[i] && hi[i] >= blo[i];
-      if (lo[i] > blo[i]) flags |= 1 << (2 * i);
-      if (hi[i] < bhi[i]) flags |= 2 << (2 * i);
+      covers = covers && lo[i] <= blo[i] && hi[i] >= bhi[i];
     }
-    return meets;
+    mf = __ballot(meets && covers);
+    mc = __ballot(meets && !covers);
   };
 
   constexpr int BX = SS::T[0] / SS::B[0];            // blocks per row (axis 0)
@@ -313,8 +316,8 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
       const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(held ? rjl : 0) * RS);
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
-        hlo[i] = irec[C + ND + i];
-        hhi[i] = irec[C + 2 * ND + i];
+        hlo[i] = irec[rec_lo(C, ND) + i];
+        hhi[i] = irec[rec_hi(C, ND) + i];
       }
     }
 
@@ -347,9 +350,9 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
       float best = 3.402823466e38f;  // FLT_MAX: out-of-window distances (+inf) never win or tie
       int bk = -1;
       if (rowfit) {
-        int flags;
-        const bool meets = test(held, hlo, hhi, blo, bhi, flags);
-        scan(__ballot(meets), hjo, flags, x, xs, I, best, bk);
+        uint64_t mf, mc;
+        test(held, hlo, hhi, blo, bhi, mf, mc);
+        scan(mf, mc, hjo, x, xs, I, best, bk);
       } else {
         int b0[ND], b1[ND];
         for (int i = 0; i < ND; ++i) {
@@ -363,12 +366,12 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
           int lo[ND], hi[ND];
           const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(bheld ? jl : 0) * RS);
           for (int i = 0; i < ND; ++i) {
-            lo[i] = irec[C + ND + i];
-            hi[i] = irec[C + 2 * ND + i];
+            lo[i] = irec[rec_lo(C, ND) + i];
+            hi[i] = irec[rec_hi(C, ND) + i];
           }
-          int flags;
-          const bool meets = test(bheld, lo, hi, blo, bhi, flags);
-          scan(__ballot(meets), jl * RS * 4, flags, x, xs, I, best, bk);
+          uint64_t mf, mc;
+          test(bheld, lo, hi, blo, bhi, mf, mc);
+          scan(mf, mc, jl * RS * 4, x, xs, I, best, bk);
         } else {
           // more centres than lanes (a crowded neighbourhood): each lane walks them
           int rc[ND];
@@ -383,7 +386,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
               const int* irec2 = reinterpret_cast<const int*>(rec);
               bool ok = true;
               for (int i = 0; i < ND; ++i)
-                ok = ok && x[i] >= irec2[C + ND + i] && x[i] <= irec2[C + 2 * ND + i];
+                ok = ok && x[i] >= irec2[rec_lo(C, ND) + i] && x[i] <= irec2[rec_hi(C, ND) + i];
               if (!ok) continue;
               float D;
               for (int i = 0; i < ND; ++i) {
@@ -394,7 +397,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
                 const float t = I[c] - rec[c];
                 D = fmaf(t, t, D);
               }
-              const int k = irec2[C + 3 * ND];
+              const int k = irec2[rec_k(C, ND)];
               if (D < best || (D == best && k < bk)) {
                 best = D;
                 bk = k;
@@ -453,7 +456,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
       const int* irec = reinterpret_cast<const int*>(a.ctab + (int64_t)k * g.rs);
       q = 0;
       for (int i = 0; i < ND; ++i) {
-        const int lo = max(irec[g.C + g.nd + i], 0), hi = min(irec[g.C + 2 * g.nd + i], g.n[i] - 1);
+        const int lo = max(irec[rec_lo(g.C, g.nd) + i], 0), hi = min(irec[rec_hi(g.C, g.nd) + i], g.n[i] - 1);
         const int t0 = lo / SS::T[i];
         const int d = tc[i] - t0;
         const bool meets = to[i] <= hi && to[i] + SS::T[i] - 1 >= lo;
