@@ -18,7 +18,6 @@ connectivity).  Prints one JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,17 +30,6 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"u8": 1, "u16": 2, "f32": 4}
 
 
-def kernel_source_hash(kernel: str) -> str:
-    """Hash of the sources a kernel class is built from (for counter staleness)."""
-    files = {"sweep": ["sweep.hip", "sslic_internal.h"],
-             "update": ["update.hip", "sslic_internal.h"]}[kernel]
-    h = hashlib.sha256()
-    for f in files:
-        with open(os.path.join(ROOT, "paper_1806_08741_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel: str, workload: str):
     """HBM bytes per launch from profiles/traffic_<kernel>_<workload>.json, if
     the counters were taken on the current source of that kernel."""
@@ -50,6 +38,7 @@ def load_traffic(kernel: str, workload: str):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    from paper_1806_08741_amd.profsum import kernel_source_hash
     if rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")

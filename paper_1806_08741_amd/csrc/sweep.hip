@@ -74,6 +74,53 @@ __device__ __forceinline__ int grid_label(const Geo& g, const int* x, int nd) {
   return (int)kk;
 }
 
+// Per-tile sums of one cluster share few 64-bit LDS words: the voxel count,
+// the coordinate sums relative to the tile and, for integer images with a
+// compile-time channel count, the channel sums.  Each field is as wide as a
+// whole tile's sum can get, so adding packed words never carries from one
+// field into the next, and a flush costs one atomic per word.
+__host__ __device__ constexpr int bits_for(uint64_t v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+template <typename T, int ND, int CC>
+struct TilePack {
+  static constexpr bool kPackCh = !std::is_same<T, float>::value && CC > 0;
+  static constexpr int kFields = 1 + ND + (kPackCh ? CC : 0);
+  int word[1 + ND + 4];
+  int shift[1 + ND + 4];
+  int nw;
+  constexpr TilePack() : word(), shift(), nw(0) {
+    uint64_t vox = 1;
+    for (int i = 0; i < ND; ++i) vox *= (uint64_t)SweepShape<ND>::T[i];
+    const uint64_t vmax = std::is_same<T, uint8_t>::value ? 255u : 65535u;
+    int w = 0, used = 0;
+    for (int f = 0; f < kFields; ++f) {
+      const uint64_t mx = f == 0 ? vox : f <= ND ? (uint64_t)(SweepShape<ND>::T[f - 1] - 1) * vox : vmax * vox;
+      const int b = bits_for(mx);
+      if (used + b > 64) {
+        ++w;
+        used = 0;
+      }
+      word[f] = w;
+      shift[f] = used;
+      used += b;
+    }
+    nw = w + 1;
+  }
+  __device__ static uint64_t field(const uint64_t* pw, int f) {
+    constexpr TilePack p{};
+    const int hi = f + 1 < kFields && p.word[f + 1] == p.word[f] ? p.shift[f + 1] : 64;
+    const uint64_t v = pw[p.word[f]] >> p.shift[f];
+    return hi - p.shift[f] >= 64 ? v : v & ((1ull << (hi - p.shift[f])) - 1);
+  }
+};
+
 template <bool FLT>
 struct RunSum {
   using type = uint32_t;
@@ -100,8 +147,13 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   const int RS = CC > 0 ? RW : g.rs;
   const int F = 1 + ND + C;
 
+  using PK = TilePack<T, ND, CC>;
+  constexpr PK pk{};
+  constexpr int NW = pk.nw;                          // packed words per entry
+  const int EW = NW + (PK::kPackCh ? 0 : C);         // + unpacked channel sums
+  constexpr int EWM = NW + (PK::kPackCh ? 0 : CM);
   __shared__ int s_keys[ACC ? HS : 1];
-  __shared__ uint64_t s_vals[ACC ? HS * FM : 1];
+  __shared__ uint64_t s_vals[ACC ? HS * EWM : 1];
 
   const int per = (int)(gridDim.x / 8);
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -111,7 +163,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
 
   if constexpr (ACC) {
     for (int i = tid; i < HS; i += kThreads) s_keys[i] = -1;
-    for (int i = tid; i < HS * F; i += kThreads) s_vals[i] = 0;
+    for (int i = tid; i < HS * EW; i += kThreads) s_vals[i] = 0;
     __syncthreads();
   }
 
@@ -147,7 +199,8 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
     int slot = -1;
     for (int p = 0; p < HS; ++p) {
       h &= HS - 1;
-      const int old = atomicCAS(&s_keys[h], -1, cur);
+      int old = s_keys[h];  // a key once written stays: look before inserting
+      if (old == -1) old = atomicCAS(&s_keys[h], -1, cur);
       if (old == -1 || old == cur) {
         slot = (int)h;
         break;
@@ -155,13 +208,25 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
       ++h;
     }
     if (slot >= 0) {
-      unsigned long long* vv = reinterpret_cast<unsigned long long*>(s_vals + slot * F);
-      atomicAdd(vv, (unsigned long long)rcnt);
-      for (int i = 0; i < ND; ++i) atomicAdd(vv + 1 + i, (unsigned long long)rco[i]);
-      for (int c = 0; c < C; ++c) {
-        if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(vv + 1 + ND + c), (double)rch[c]);
-        else atomicAdd(vv + 1 + ND + c, (unsigned long long)rch[c]);
+      uint64_t pw[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) pw[w] = 0;
+      pw[pk.word[0]] |= (uint64_t)rcnt << pk.shift[0];
+#pragma unroll
+      for (int i = 0; i < ND; ++i) pw[pk.word[1 + i]] |= (uint64_t)rco[i] << pk.shift[1 + i];
+      unsigned long long* vv = reinterpret_cast<unsigned long long*>(s_vals + slot * EW);
+      if constexpr (PK::kPackCh) {
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+          pw[pk.word[1 + ND + c]] |= (uint64_t)rch[c] << pk.shift[1 + ND + c];
+      } else {
+        for (int c = 0; c < C; ++c) {
+          if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(vv + NW + c), (double)rch[c]);
+          else atomicAdd(vv + NW + c, (unsigned long long)rch[c]);
+        }
       }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) atomicAdd(vv + w, (unsigned long long)pw[w]);
     } else {  // table full: global accumulators (coordinates made absolute)
       unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)cur * F);
       atomicAdd(gg, (unsigned long long)rcnt);
@@ -445,12 +510,16 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   for (int s = tid; s < HS; s += kThreads) {
     const int k = s_keys[s];
     if (k < 0) continue;
-    const uint64_t* vv = s_vals + s * F;
-    const uint64_t n = vv[0];
+    const uint64_t* vv = s_vals + s * EW;
+    const uint64_t n = PK::field(vv, 0);
     uint64_t out[FM];
     out[0] = n;
-    for (int i = 0; i < ND; ++i) out[1 + i] = vv[1 + i] + n * (uint64_t)to[i];
-    for (int c = 0; c < C; ++c) out[1 + ND + c] = vv[1 + ND + c];
+    for (int i = 0; i < ND; ++i) out[1 + i] = PK::field(vv, 1 + i) + n * (uint64_t)to[i];
+    if constexpr (PK::kPackCh) {
+      for (int c = 0; c < CM; ++c) out[1 + ND + c] = PK::field(vv, 1 + ND + c);
+    } else {
+      for (int c = 0; c < C; ++c) out[1 + ND + c] = vv[NW + c];
+    }
     int q = -1;
     if (a.slots) {
       const int* irec = reinterpret_cast<const int*>(a.ctab + (int64_t)k * g.rs);
