@@ -72,6 +72,10 @@ typedef struct {
                                  every iteration run (Sec. 3.2), 0 after a stop */
   int32_t* iters_done_dev;    /* device int32 or NULL: iterations actually run */
   int32_t* n_labels_dev;      /* device int32 or NULL: labels in use after stage 3 */
+  int no_graph;               /* sslic_run_batch: 1 = enqueue the launches directly
+                                 instead of replaying a captured HIP graph */
+  int no_autotune;            /* sslic_run_batch: 1 = default tile shapes instead of
+                                 the ones timed per (ndim, channels, dtype, S) */
 } sslic_options;
 
 /* Create a context bound to HIP device `device_ordinal`.
@@ -122,14 +126,27 @@ typedef struct {
   double* centres;    /* device double [K][channels + ndim] */
   int64_t* counts;    /* device int64 [K] or NULL */
   double* residuals;  /* device double [iterations] or NULL */
+  int32_t* iters_done;/* device int32 or NULL: iterations this image ran */
 } sslic_image_desc;
 
-/* Many independent images in one pass (the batched form): seeding, then the
- * iterations of every image interleaved over one flat work-list of tiles per
- * launch, each image stopping on its own residual test (opt->tol), then
- * connectivity per image unless opt->no_connectivity.  Each image's result is
- * the one sslic_run gives for it alone.  opt->init_centres and the *_dev
- * fields are ignored; use the per-image descriptor fields.
+/* Many independent images in one pass (the batched form).  Images may differ
+ * in size, ndim, channels, dtype, S, m and iterations.  Seeding, then the
+ * iterations of every image interleaved: per iteration one persistent launch
+ * per group of images sharing (dtype, ndim, channels, tile shape) walks a
+ * flat work-list of their tiles; each image stops on its own residual test
+ * (opt->tol) or after its own `iterations`; then connectivity per image
+ * unless opt->no_connectivity.  Each image's result is the one sslic_run
+ * gives for it alone (bit-identical labels and centres for integer images;
+ * float images may differ in the last bits of FP64 sums).
+ *   Tile shapes: the first time a (ndim, channels, dtype, S) appears, the
+ * candidate shapes are timed on the largest such image of the batch and the
+ * fastest is kept for the context's lifetime (opt->no_autotune: defaults).
+ * This first call waits for the stream.
+ *   Graphs: the launches are captured into a HIP graph; a later call with the
+ * same descriptors and options on the same context replays it, reading the
+ * images and writing the outputs at the same addresses (opt->no_graph:
+ * enqueue directly).  The batch workspace is separate from the one sslic_run
+ * uses.  opt->init_centres and the opt *_dev fields are ignored.
  * n_labels_out: host int32 [n] or NULL (makes the call wait). */
 int sslic_run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n,
                     const sslic_options* opt, int32_t* n_labels_out, sslic_stream_t stream);

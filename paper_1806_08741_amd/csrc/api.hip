@@ -10,28 +10,17 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/sslic.h"
 #include "../../include/sslic_profile.h"
 #include "../../include/sslic_steps.h"
-#include "sslic_internal.h"
+#include "sslic_ctx.h"
 
 using namespace sslic;
 
-struct sslic_ctx {
-  int device = 0;
-  char* ws = nullptr;   // device workspace
-  size_t ws_size = 0;
-  int32_t* host_ints = nullptr;  // pinned staging for *_out scalars
-  // event timing of kernel classes (sslic_profile.h)
-  bool prof = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> marks;
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace sslic {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -42,14 +31,6 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_TRY(expr)                                                               \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      return fail(SSLIC_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
-                  __FILE__, __LINE__);                                              \
-  } while (0)
 
 int64_t grid_count(int64_t n, int64_t s) {
   int64_t k = (2 * n + s) / (2 * s);
@@ -103,13 +84,7 @@ int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, con
   return SSLIC_OK;
 }
 
-constexpr size_t kAlign = 256;
 size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-
-struct Layout {
-  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, brec, scan_part, acc, part, res_acc, flags;
-  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, total;
-};
 
 Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   Layout L{};
@@ -267,7 +242,7 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   return SSLIC_OK;
 }
 
-}  // namespace
+}  // namespace sslic
 
 extern "C" {
 
@@ -300,6 +275,7 @@ void sslic_destroy(sslic_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  release_batch(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->host_ints) (void)hipHostFree(ctx->host_ints);
   delete ctx;
@@ -362,20 +338,7 @@ int sslic_run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const
                     int32_t* n_labels_out, sslic_stream_t stream) {
   if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
   if (n < 0 || (n > 0 && !images)) return fail(SSLIC_EINVAL, "bad image list");
-  sslic_options o{};
-  if (opt) o = *opt;
-  for (int i = 0; i < n; ++i) {
-    const sslic_image_desc& d = images[i];
-    sslic_options oi{};
-    oi.tol = o.tol;
-    oi.no_connectivity = o.no_connectivity;
-    oi.residuals = d.residuals;
-    int rc = sslic_run(ctx, d.image, d.ndim, d.dims, d.channels, d.dtype, d.S, d.m, d.iterations, &oi,
-                       d.labels, d.centres, d.counts, n_labels_out ? n_labels_out + i : nullptr,
-                       nullptr, stream);
-    if (rc) return rc;
-  }
-  return SSLIC_OK;
+  return run_batch(ctx, images, n, opt, n_labels_out, (hipStream_t)stream);
 }
 
 int sslic_seed(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, int channels,

@@ -77,10 +77,9 @@ __device__ __forceinline__ G grad_any(const Geo& g, const T* img, const int* p, 
 }
 
 template <typename T>
-__global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict__ cen) {
+__device__ __forceinline__ void seed_one(const Geo& g, const T* __restrict__ img, double* __restrict__ cen,
+                                         int64_t k) {
   using G = typename std::conditional<std::is_same<T, float>::value, double, int64_t>::type;
-  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= g.K) return;
   const int nd = g.nd;
   int s[kMaxDim], q[kMaxDim], best[kMaxDim];
   int64_t r = k;
@@ -115,6 +114,23 @@ __global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict
   for (int i = 0; i < g.nd_out; ++i) row[g.C + i] = (double)best[i];
 }
 
+template <typename T>
+__global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict__ cen) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  seed_one<T>(g, img, cen, k);
+}
+
+// clusters [k0, k1) of a batch, all of one pixel type
+template <typename T>
+__global__ void seed_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ cl_img,
+                                  int64_t k0, int64_t k1) {
+  int64_t gk = k0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gk >= k1) return;
+  const BImg& d = imgs[cl_img[gk]];
+  seed_one<T>(d.g, reinterpret_cast<const T*>(d.img), d.cen, gk - d.koff);
+}
+
 __global__ void grid_labels_kernel(Geo g, int32_t* __restrict__ labels) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N;
        v += (int64_t)gridDim.x * blockDim.x) {
@@ -141,7 +157,8 @@ __device__ __forceinline__ int floordiv(int a, int b) {
   return (q * b > a) ? q - 1 : q;
 }
 
-__device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_t k, const Iter& it) {
+__device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_t k, const Iter& it,
+                                         int64_t binoff = 0) {
   float* rec = it.ctab + k * g.rs;
   int32_t* irec = reinterpret_cast<int32_t*>(rec);
   for (int c = 0; c < g.C; ++c) rec[c] = (float)row[c];
@@ -168,8 +185,34 @@ __device__ __forceinline__ void prep_one(const Geo& g, const double* row, int64_
     bin += b * g.bst[i];
   }
   irec[rec_k(g.C, g.nd)] = (int32_t)k;
-  it.bin_of[k] = (int32_t)bin;
-  atomicAdd(&it.bin_cnt[bin], 1);
+  it.bin_of[k] = (int32_t)(bin + binoff);
+  atomicAdd(&it.bin_cnt[bin + binoff], 1);
+}
+
+// The image's view of the batch's shared tables: its records and bins at its
+// offsets, its own accumulators and tile slots.
+__device__ __forceinline__ Iter batch_iter(const BImg& d, float* ctab, int32_t* bin_of,
+                                           int32_t* bin_cnt) {
+  Iter it{};
+  it.ctab = ctab + d.koff * d.g.rs;
+  it.bin_of = bin_of + d.koff;
+  it.bin_cnt = bin_cnt;
+  it.acc = d.a.acc;
+  it.part = d.a.part;
+  it.res_acc = d.res;
+  it.done = d.flags;
+  it.iters = d.flags + 1;
+  return it;
+}
+
+__global__ void prep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ cl_img,
+                                  int64_t K, float* ctab, int32_t* bin_of, int32_t* bin_cnt) {
+  int64_t gk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gk >= K) return;
+  const BImg& d = imgs[cl_img[gk]];
+  if (d.flags[0]) return;
+  const int64_t k = gk - d.koff;
+  prep_one(d.g, d.cen + k * d.g.row, k, batch_iter(d, ctab, bin_of, bin_cnt), d.binoff);
 }
 
 __global__ void prep_kernel(Geo g, const double* __restrict__ cen, Iter it) {
@@ -254,6 +297,7 @@ __global__ void scatter_kernel(Geo g, Iter it) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= g.K) return;
   int b = it.bin_of[k];
+  if (b < 0) return;  // a cluster of a finished image (batches)
   int pos = it.bin_start[b] + atomicAdd(&it.bin_cnt[b], 1);
   it.bin_items[pos] = (int32_t)k;
 }
@@ -297,18 +341,20 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
+// The reduce step of cluster k: accumulators (and, with use_part, the tile
+// slots of the tiles its window meets, as the sweep chose them) -> new centre
+// in FP64, count, residual term (e_sum, e_cnt); then the next iteration's
+// record and bin when prep_next.
 template <int ND, int CC, bool FLT>
-__global__ void __launch_bounds__(kThreads)
-finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, Iter it, int t,
-                int prep_next, int use_part, TileDims td) {
-  if (*it.done) return;
+__device__ __forceinline__ void finalize_one(const Geo& g, double* __restrict__ cen,
+                                             int64_t* __restrict__ counts, const Iter& it,
+                                             int64_t k, int prep_next, int use_part,
+                                             const int* tdT, int64_t binoff, double& e_sum,
+                                             double& e_cnt) {
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   const int C = CC > 0 ? CC : g.C;
   const int F = 1 + ND + C;
-  __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
-  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  double e_sum = 0.0, e_cnt = 0.0;
-  if (k < g.K) {
+
     uint64_t* a = it.acc + k * F;
     uint64_t si[1 + ND];
     uint64_t sc[CM];
@@ -330,7 +376,7 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
         lo[i] = max(irec[rec_lo(C, ND) + i], 0);
         hi[i] = min(irec[rec_hi(C, ND) + i], g.n[i] - 1);
         any = any && lo[i] <= hi[i];
-        t0[i] = lo[i] / td.T[i];
+        t0[i] = lo[i] / tdT[i];
       }
       if (any) {
 #pragma unroll
@@ -338,7 +384,7 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
           bool meets = true;
 #pragma unroll
           for (int i = 0; i < ND; ++i) {
-            if ((q >> i) & 1) meets = meets && (t0[i] + 1) * td.T[i] <= hi[i];
+            if ((q >> i) & 1) meets = meets && (t0[i] + 1) * tdT[i] <= hi[i];
           }
           if (!meets) continue;
           uint64_t* p = it.part + (k * (1 << ND) + q) * F;
@@ -374,8 +420,18 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
       e_cnt = 1.0;
     }
     if (counts) counts[k] = (int64_t)n;
-    if (prep_next) prep_one(g, row, k, it);
+    if (prep_next) prep_one(g, row, k, it, binoff);
   }
+
+template <int ND, int CC, bool FLT>
+__global__ void __launch_bounds__(kThreads)
+finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, Iter it, int t,
+                int prep_next, int use_part, TileDims td) {
+  if (*it.done) return;
+  __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double e_sum = 0.0, e_cnt = 0.0;
+  if (k < g.K) finalize_one<ND, CC, FLT>(g, cen, counts, it, k, prep_next, use_part, td.T, 0, e_sum, e_cnt);
   e_sum = warp_sum(e_sum);
   e_cnt = warp_sum(e_cnt);
   int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
@@ -404,6 +460,70 @@ __global__ void residual_finish_kernel(Iter it, int t, double tol, double* resid
   if (residuals) residuals[t] = e;
   *it.iters = t + 1;
   if (e < tol) *it.done = 1;
+}
+
+// Reduce step of the clusters [k0, k1) of a batch group.  Residual partials
+// go to each image's own (sum, count) pair; a wave whose lanes all belong to
+// one image adds its total once.
+template <int ND, int CC, bool FLT>
+__global__ void __launch_bounds__(kThreads)
+finalize_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ cl_img, int64_t k0,
+                      int64_t k1, float* ctab, int32_t* bin_of, int32_t* bin_cnt, int t) {
+  const int64_t gk = k0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = gk < k1;
+  const int im = in ? cl_img[gk] : -1;
+  double e_sum = 0.0, e_cnt = 0.0;
+  if (in) {
+    const BImg& d = imgs[im];
+    const bool next = t + 1 < d.iterations;
+    if (!d.flags[0]) {
+      const int64_t k = gk - d.koff;
+      finalize_one<ND, CC, FLT>(d.g, d.cen, d.counts, batch_iter(d, ctab, bin_of, bin_cnt), k,
+                                next, d.a.slots, d.tdim, d.binoff, e_sum, e_cnt);
+    }
+    // an image that has stopped takes no part in later bin sorts
+    if (d.flags[0] || !next) bin_of[gk] = -1;
+  }
+  const int first = __builtin_amdgcn_readfirstlane(im);
+  if (__all(im == first)) {
+    e_sum = warp_sum(e_sum);
+    e_cnt = warp_sum(e_cnt);
+    if (threadIdx.x % 64 == 0 && first >= 0 && e_cnt > 0.0) {
+      atomicAdd(&imgs[first].res[2 * t], e_sum);
+      atomicAdd(&imgs[first].res[2 * t + 1], e_cnt);
+    }
+  } else if (in && e_cnt > 0.0) {
+    atomicAdd(&imgs[im].res[2 * t], e_sum);
+    atomicAdd(&imgs[im].res[2 * t + 1], e_cnt);
+  }
+}
+
+// Per image: residual of iteration t, iteration count, done flag (converged,
+// or its own iteration count reached).
+__global__ void residual_finish_batch_kernel(const BImg* __restrict__ imgs, int n, int t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BImg& d = imgs[i];
+  if (d.flags[0]) return;
+  const double s = d.res[2 * t], c = d.res[2 * t + 1];
+  const double e = c > 0.0 ? s / c : 0.0;
+  if (d.residuals) d.residuals[t] = e;
+  d.flags[1] = t + 1;
+  if (e < d.tol || t + 1 >= d.iterations) d.flags[0] = 1;
+}
+
+// residuals[t] = 0 for every t of every image (iterations after a stop read 0)
+__global__ void batch_zero_residuals_kernel(const BImg* __restrict__ imgs, int n, int tmax) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= (int64_t)n * tmax) return;
+  const BImg& d = imgs[j / tmax];
+  const int t = (int)(j % tmax);
+  if (d.residuals && t < d.iterations) d.residuals[t] = 0.0;
+}
+
+__global__ void batch_outputs_kernel(const BImg* __restrict__ imgs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && imgs[i].iters_out) *imgs[i].iters_out = imgs[i].flags[1];
 }
 
 }  // namespace
@@ -469,6 +589,71 @@ hipError_t launch_finalize(const Geo& g, double* cen, int64_t* counts, const Ite
   }
 #undef SSLIC_FIN_C
 #undef SSLIC_FIN
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_batch(int dtype, const BImg* imgs, const int32_t* cl_img, int64_t k0,
+                             int64_t k1, hipStream_t s) {
+  if (k1 <= k0) return hipSuccess;
+  const int nb = blocks_for(k1 - k0);
+  switch (dtype) {
+    case kU8: seed_batch_kernel<uint8_t><<<nb, kThreads, 0, s>>>(imgs, cl_img, k0, k1); break;
+    case kU16: seed_batch_kernel<uint16_t><<<nb, kThreads, 0, s>>>(imgs, cl_img, k0, k1); break;
+    default: seed_batch_kernel<float><<<nb, kThreads, 0, s>>>(imgs, cl_img, k0, k1); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_batch(const BImg* imgs, const int32_t* cl_img, int64_t K, float* ctab,
+                             int32_t* bin_of, int32_t* bin_cnt, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  prep_batch_kernel<<<blocks_for(K), kThreads, 0, s>>>(imgs, cl_img, K, ctab, bin_of, bin_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(int dtype, int nd, int C, const BImg* imgs, const int32_t* cl_img,
+                                 int64_t k0, int64_t k1, float* ctab, int32_t* bin_of,
+                                 int32_t* bin_cnt, int t, hipStream_t s) {
+  if (k1 <= k0) return hipSuccess;
+  const unsigned nb = blocks_for(k1 - k0);
+  const bool flt = dtype == kF32;
+#define SSLIC_FINB(ND, CC)                                                                       \
+  (flt ? (finalize_batch_kernel<ND, CC, true><<<nb, kThreads, 0, s>>>(imgs, cl_img, k0, k1, ctab,  \
+                                                                     bin_of, bin_cnt, t), 0)    \
+       : (finalize_batch_kernel<ND, CC, false><<<nb, kThreads, 0, s>>>(imgs, cl_img, k0, k1, ctab, \
+                                                                      bin_of, bin_cnt, t), 0))
+#define SSLIC_FINB_C(ND)                      \
+  switch (C) {                                \
+    case 1: SSLIC_FINB(ND, 1); break;         \
+    case 3: SSLIC_FINB(ND, 3); break;         \
+    case 4: SSLIC_FINB(ND, 4); break;         \
+    default: SSLIC_FINB(ND, 0); break;        \
+  }
+  switch (nd) {
+    case 2: SSLIC_FINB_C(2); break;
+    case 3: SSLIC_FINB_C(3); break;
+    default: SSLIC_FINB_C(4); break;
+  }
+#undef SSLIC_FINB_C
+#undef SSLIC_FINB
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_finish_batch(const BImg* imgs, int n, int t, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  residual_finish_batch_kernel<<<blocks_for(n), kThreads, 0, s>>>(imgs, n, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_zero_residuals(const BImg* imgs, int n, int tmax, hipStream_t s) {
+  if (n <= 0 || tmax <= 0) return hipSuccess;
+  batch_zero_residuals_kernel<<<blocks_for((int64_t)n * tmax), kThreads, 0, s>>>(imgs, n, tmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_outputs(const BImg* imgs, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  batch_outputs_kernel<<<blocks_for(n), kThreads, 0, s>>>(imgs, n);
   return hipGetLastError();
 }
 

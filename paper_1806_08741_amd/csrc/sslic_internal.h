@@ -99,11 +99,57 @@ struct SweepArgs {
   int slots;  // 1: per-cluster tile slots; 0: tiles narrower than a window, atomics only
 };
 // assignment of every voxel (labels); with `accumulate`, also the per-cluster
-// sums into it.part (tile slots) / it.acc (atomics)
+// sums into it.part (tile slots) / it.acc (atomics).  `var` picks the tile
+// shape (0 default, 1 small).
 hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels,
-                        int first, int accumulate, hipStream_t s);
-int sweep_slots(const Geo& g);              // whether the sweep uses tile slots
-void sweep_tile_shape(int nd, int* T);      // its tile extent per axis
+                        int first, int accumulate, hipStream_t s, int var = 0);
+constexpr int kTileVars = 2;
+int sweep_slots(const Geo& g, int var = 0);          // whether the sweep uses tile slots
+void sweep_tile_shape(int nd, int* T, int var = 0);  // its tile extent per axis
+
+// ---- batched form ----------------------------------------------------------
+// One image of a batch.  The batch shares one centre table, bin index and
+// record array (global cluster index = koff + k, global bin = binoff + bin,
+// record stride g.rs common to the batch); accumulators, tile slots, residual
+// partials and flags are the image's own.
+struct BImg {
+  Geo g;
+  SweepArgs a;            // a.bstart unused (bin_start + binoff), a.first per launch
+  const void* img;
+  double* cen;            // caller's [K][C + n]
+  int64_t* counts;        // caller's [K] or null
+  double* residuals;      // caller's [iterations] or null
+  int32_t* iters_out;     // caller's device int32 or null
+  double* res;            // [iterations][2] residual partials
+  int32_t* flags;         // [0] done, [1] iterations run
+  int64_t koff;           // first global cluster
+  int64_t binoff;         // first global bin
+  int tile_off;           // first tile in its group's work-list (global tile numbering)
+  int iterations;
+  double tol;
+  int tdim[kMaxDim];      // tile extent of its group
+};
+// sweep of one group's tiles (persistent; grid = workgroups)
+hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
+                              const int32_t* tile_img, int tile0, int ntiles,
+                              const int32_t* bin_start, const float* brec, int first,
+                              unsigned grid, hipStream_t s);
+// seeding of the clusters [k0, k1) of one pixel type (cluster -> image map cl_img)
+hipError_t launch_seed_batch(int dtype, const BImg* imgs, const int32_t* cl_img, int64_t k0,
+                             int64_t k1, hipStream_t s);
+// records and bin counts of every cluster of images not done
+hipError_t launch_prep_batch(const BImg* imgs, const int32_t* cl_img, int64_t K, float* ctab,
+                             int32_t* bin_of, int32_t* bin_cnt, hipStream_t s);
+// the reduce step of one group ([k0, k1) share nd, C, pixel type)
+hipError_t launch_finalize_batch(int dtype, int nd, int C, const BImg* imgs, const int32_t* cl_img,
+                                 int64_t k0, int64_t k1, float* ctab, int32_t* bin_of,
+                                 int32_t* bin_cnt, int t, hipStream_t s);
+// residual, done flags and iteration counts of every image
+hipError_t launch_residual_finish_batch(const BImg* imgs, int n, int t, hipStream_t s);
+// iteration counts to the callers' device ints
+hipError_t launch_batch_outputs(const BImg* imgs, int n, hipStream_t s);
+// every image's residuals to 0
+hipError_t launch_batch_zero_residuals(const BImg* imgs, int n, int tmax, hipStream_t s);
 hipError_t launch_update(const Geo& g, const void* img, const int32_t* labels,
                          const Iter& it, hipStream_t s);
 // accumulators (and, with `use_part`, the sweep's tile slots) -> new centres,

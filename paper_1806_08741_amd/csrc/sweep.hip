@@ -37,31 +37,51 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-template <int ND>
-struct SweepShape;
+// Tile shapes: VAR 0 is the default; VAR 1 is a smaller tile that the batch
+// autotuner may pick for small images.
+template <int ND, int VAR>
+struct Shape;
 template <>
-struct SweepShape<2> {
+struct Shape<2, 0> {
   static constexpr int T[2] = {64, 64};
   static constexpr int B[2] = {8, 8};
   static constexpr int kHash = 256;
 };
 template <>
-struct SweepShape<3> {
+struct Shape<2, 1> {
+  static constexpr int T[2] = {32, 32};
+  static constexpr int B[2] = {8, 8};
+  static constexpr int kHash = 128;
+};
+template <>
+struct Shape<3, 0> {
   static constexpr int T[3] = {32, 32, 32};
   static constexpr int B[3] = {4, 4, 4};
   static constexpr int kHash = 512;
 };
 template <>
-struct SweepShape<4> {
+struct Shape<3, 1> {
+  static constexpr int T[3] = {16, 16, 16};
+  static constexpr int B[3] = {4, 4, 4};
+  static constexpr int kHash = 256;
+};
+template <>
+struct Shape<4, 0> {
   static constexpr int T[4] = {16, 16, 8, 8};
   static constexpr int B[4] = {4, 4, 2, 2};
   static constexpr int kHash = 512;
 };
+template <>
+struct Shape<4, 1> {
+  static constexpr int T[4] = {8, 8, 8, 8};
+  static constexpr int B[4] = {4, 4, 2, 2};
+  static constexpr int kHash = 256;
+};
 
-template <int ND>
+template <class SH, int ND>
 __host__ __device__ constexpr int blocks_per_tile() {
   int n = 1;
-  for (int i = 0; i < ND; ++i) n *= SweepShape<ND>::T[i] / SweepShape<ND>::B[i];
+  for (int i = 0; i < ND; ++i) n *= SH::T[i] / SH::B[i];
   return n;
 }
 
@@ -88,7 +108,7 @@ __host__ __device__ constexpr int bits_for(uint64_t v) {
   return b;
 }
 
-template <typename T, int ND, int CC>
+template <typename T, int ND, int CC, class SH>
 struct TilePack {
   static constexpr bool kPackCh = !std::is_same<T, float>::value && CC > 0;
   static constexpr int kFields = 1 + ND + (kPackCh ? CC : 0);
@@ -97,11 +117,11 @@ struct TilePack {
   int nw;
   constexpr TilePack() : word(), shift(), nw(0) {
     uint64_t vox = 1;
-    for (int i = 0; i < ND; ++i) vox *= (uint64_t)SweepShape<ND>::T[i];
+    for (int i = 0; i < ND; ++i) vox *= (uint64_t)SH::T[i];
     const uint64_t vmax = std::is_same<T, uint8_t>::value ? 255u : 65535u;
     int w = 0, used = 0;
     for (int f = 0; f < kFields; ++f) {
-      const uint64_t mx = f == 0 ? vox : f <= ND ? (uint64_t)(SweepShape<ND>::T[f - 1] - 1) * vox : vmax * vox;
+      const uint64_t mx = f == 0 ? vox : f <= ND ? (uint64_t)(SH::T[f - 1] - 1) * vox : vmax * vox;
       const int b = bits_for(mx);
       if (used + b > 64) {
         ++w;
@@ -121,6 +141,13 @@ struct TilePack {
   }
 };
 
+// 64-bit LDS words per table entry
+template <typename T, int ND, int CC, class SH>
+__host__ __device__ constexpr int entry_words() {
+  using PK = TilePack<T, ND, CC, SH>;
+  return PK{}.nw + (PK::kPackCh ? 0 : (CC > 0 ? CC : kMaxChan));
+}
+
 template <bool FLT>
 struct RunSum {
   using type = uint32_t;
@@ -130,34 +157,30 @@ struct RunSum<true> {
   using type = double;
 };
 
-template <typename T, int ND, int CC, bool ACC>
-__global__ void __launch_bounds__(kThreads)
-sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
-             const float* __restrict__ brec, SweepArgs a) {
-  if (*a.done) return;
-  using SS = SweepShape<ND>;
+// One tile of the sweep: the assignment of its voxels and, with ACC, the
+// per-cluster sums of the tile into the cluster's tile slot or accumulators.
+// s_keys / s_vals: the workgroup's LDS table (SH::kHash entries).
+template <typename T, int ND, int CC, bool ACC, class SH>
+__device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ img,
+                                           const int32_t* __restrict__ bstart,
+                                           const float* __restrict__ brec, const SweepArgs& a,
+                                           int first, int tile, int* s_keys, uint64_t* s_vals) {
+  using SS = SH;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
-  constexpr int RW = (CM + 3 * ND + 1 + 3) & ~3;
   constexpr int RN = CM + 3 * ND + 1;  // record words read
   constexpr int HS = SS::kHash;
   constexpr int FM = 1 + ND + CM;
   constexpr bool FLT = std::is_same<T, float>::value;
   using RT = typename RunSum<FLT>::type;
   const int C = CC > 0 ? CC : g.C;
-  const int RS = CC > 0 ? RW : g.rs;
+  const int RS = g.rs;
   const int F = 1 + ND + C;
 
-  using PK = TilePack<T, ND, CC>;
+  using PK = TilePack<T, ND, CC, SH>;
   constexpr PK pk{};
   constexpr int NW = pk.nw;                          // packed words per entry
   const int EW = NW + (PK::kPackCh ? 0 : C);         // + unpacked channel sums
-  constexpr int EWM = NW + (PK::kPackCh ? 0 : CM);
-  __shared__ int s_keys[ACC ? HS : 1];
-  __shared__ uint64_t s_vals[ACC ? HS * EWM : 1];
 
-  const int per = (int)(gridDim.x / 8);
-  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (tile >= a.ntiles) return;
   const int tid = threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
 
@@ -344,7 +367,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   };
 
   constexpr int BX = SS::T[0] / SS::B[0];            // blocks per row (axis 0)
-  constexpr int NROW = blocks_per_tile<ND>() / BX;   // block rows per tile
+  constexpr int NROW = blocks_per_tile<SS, ND>() / BX;  // block rows per tile
   static_assert(NROW % kWaves == 0, "rows must split evenly over waves");
   constexpr int RPW = NROW / kWaves;
 
@@ -479,7 +502,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
         }
       }
       if (valid) {
-        if (bk < 0) bk = a.first ? grid_label(g, x, ND) : a.labels[v];
+        if (bk < 0) bk = first ? grid_label(g, x, ND) : a.labels[v];
         a.labels[v] = bk;
         if constexpr (ACC) {
           if (bk != cur) {
@@ -551,9 +574,47 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   }
 }
 
+template <typename T, int ND, int CC, bool ACC>
+__global__ void __launch_bounds__(kThreads)
+sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
+             const float* __restrict__ brec, SweepArgs a) {
+  if (*a.done) return;
+  using SH = Shape<ND, 0>;
+  __shared__ int s_keys[ACC ? SH::kHash : 1];
+  __shared__ uint64_t s_vals[ACC ? SH::kHash * entry_words<T, ND, CC, SH>() : 1];
+  const int per = (int)(gridDim.x / 8);
+  const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (tile >= a.ntiles) return;
+  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, brec, a, a.first, tile, s_keys, s_vals);
+}
+
+// Persistent form over the flat tile work-list of a group of images (same
+// pixel type, dimensionality, channel count and tile shape).  The list is cut
+// into 8 contiguous chunks, one per XCD (workgroups are dealt to XCDs round
+// robin), so neighbouring tiles of an image share an L2; the workgroups of an
+// XCD stride through its chunk.  Tiles of converged images are skipped.
+template <typename T, int ND, int CC, class SH>
+__global__ void __launch_bounds__(kThreads)
+sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
+                   int ntiles, const int32_t* __restrict__ bin_start,
+                   const float* __restrict__ brec, int first) {
+  __shared__ int s_keys[SH::kHash];
+  __shared__ uint64_t s_vals[SH::kHash * entry_words<T, ND, CC, SH>()];
+  const int xcd = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
+  const int chunk = (ntiles + 7) / 8;
+  const int end = min((xcd + 1) * chunk, ntiles);
+  for (int t = xcd * chunk + (int)(blockIdx.x / 8); t < end; t += per) {
+    const BImg& d = imgs[tile_img[tile0 + t]];
+    if (d.flags[0]) continue;
+    __syncthreads();  // the previous tile's table is read out
+    sweep_tile<T, ND, CC, true, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
+                                   brec, d.a, first, tile0 + t - d.tile_off, s_keys, s_vals);
+  }
+}
+
 template <typename T, int ND, bool ACC>
 hipError_t dispatch_c(const Geo& g, const void* img, SweepArgs a, hipStream_t s) {
-  using SS = SweepShape<ND>;
+  using SS = Shape<ND, 0>;
   int nt = 1;
   a.slots = 1;
   for (int i = 0; i < kMaxDim; ++i) a.nt[i] = 1;
@@ -592,23 +653,70 @@ hipError_t dispatch(const Geo& g, const void* img, const SweepArgs& a, hipStream
   }
 }
 
+template <typename T, int ND, int CC, int VAR>
+hipError_t batch_launch(const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
+                        const int32_t* bin_start, const float* brec, int first, unsigned grid,
+                        hipStream_t s) {
+  sweep_batch_kernel<T, ND, CC, Shape<ND, VAR>><<<grid, kThreads, 0, s>>>(
+      imgs, tile_img, tile0, ntiles, bin_start, brec, first);
+  return hipGetLastError();
+}
+
+template <typename T, int ND, int CC>
+hipError_t batch_var(int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
+                     const int32_t* bin_start, const float* brec, int first, unsigned grid,
+                     hipStream_t s) {
+  return var == 1 ? batch_launch<T, ND, CC, 1>(imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s)
+                  : batch_launch<T, ND, CC, 0>(imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+}
+
+template <typename T, int ND>
+hipError_t batch_c(int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
+                   const int32_t* bin_start, const float* brec, int first, unsigned grid,
+                   hipStream_t s) {
+  switch (C) {
+    case 1: return batch_var<T, ND, 1>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case 3: return batch_var<T, ND, 3>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case 4: return batch_var<T, ND, 4>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    default: return batch_var<T, ND, 0>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+  }
+}
+
+template <typename T>
+hipError_t batch_nd(int nd, int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0,
+                    int ntiles, const int32_t* bin_start, const float* brec, int first,
+                    unsigned grid, hipStream_t s) {
+  switch (nd) {
+    case 2: return batch_c<T, 2>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case 3: return batch_c<T, 3>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    default: return batch_c<T, 4>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+  }
+}
+
+template <int ND>
+void shape_of(int var, int* T) {
+  for (int i = 0; i < ND; ++i) T[i] = var == 1 ? Shape<ND, 1>::T[i] : Shape<ND, 0>::T[i];
+}
+
 }  // namespace
 
-int sweep_slots(const Geo& g) {
-  for (int i = 0; i < g.nd; ++i) {
-    int T = g.nd == 2 ? SweepShape<2>::T[i] : g.nd == 3 ? SweepShape<3>::T[i] : SweepShape<4>::T[i];
-    if (T < 2 * g.S[i] + 1) return 0;
-  }
+void sweep_tile_shape(int nd, int* T, int var) {
+  if (nd == 2) shape_of<2>(var, T);
+  else if (nd == 3) shape_of<3>(var, T);
+  else shape_of<4>(var, T);
+}
+
+int sweep_slots(const Geo& g, int var) {
+  int T[kMaxDim];
+  sweep_tile_shape(g.nd, T, var);
+  for (int i = 0; i < g.nd; ++i)
+    if (T[i] < 2 * g.S[i] + 1) return 0;
   return 1;
 }
 
-void sweep_tile_shape(int nd, int* T) {
-  for (int i = 0; i < nd; ++i)
-    T[i] = nd == 2 ? SweepShape<2>::T[i] : nd == 3 ? SweepShape<3>::T[i] : SweepShape<4>::T[i];
-}
-
 hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels, int first,
-                        int accumulate, hipStream_t s) {
+                        int accumulate, hipStream_t s, int var) {
+  (void)var;  // the single-image path uses the default tile
   SweepArgs a{};
   a.bstart = it.bin_start;
   a.brec = it.brec;
@@ -619,6 +727,19 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
   a.part = it.part;
   a.acc = it.acc;
   return accumulate ? dispatch<true>(g, img, a, s) : dispatch<false>(g, img, a, s);
+}
+
+hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
+                              const int32_t* tile_img, int tile0, int ntiles,
+                              const int32_t* bin_start, const float* brec, int first,
+                              unsigned grid, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  grid = (grid + 7) / 8 * 8;
+  switch (dtype) {
+    case kU8: return batch_nd<uint8_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case kU16: return batch_nd<uint16_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    default: return batch_nd<float>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+  }
 }
 
 }  // namespace sslic

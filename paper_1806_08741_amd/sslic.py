@@ -35,13 +35,13 @@ class SslicError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("tol", D), ("no_connectivity", I), ("init_centres", P), ("residuals", P),
-                ("iters_done_dev", P), ("n_labels_dev", P)]
+                ("iters_done_dev", P), ("n_labels_dev", P), ("no_graph", I), ("no_autotune", I)]
 
 
 class ImageDesc(ctypes.Structure):
     _fields_ = [("image", P), ("ndim", I), ("dims", I64 * 4), ("channels", I), ("dtype", I),
                 ("S", ctypes.c_int32 * 4), ("m", D), ("iterations", I), ("labels", P),
-                ("centres", P), ("counts", P), ("residuals", P)]
+                ("centres", P), ("counts", P), ("residuals", P), ("iters_done", P)]
 
 
 _lib = None
@@ -165,7 +165,7 @@ class Context:
         if counts is None:
             counts = torch.empty(K, dtype=torch.int64, device=dev)
         res = torch.zeros(iterations, dtype=torch.float64, device=dev) if residuals else None
-        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None)
+        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None, 0, 0)
         if init_centres is not None:
             ic = init_centres.to(device=dev, dtype=torch.float64).contiguous()
             o.init_centres = ic.data_ptr()
@@ -188,10 +188,14 @@ class Context:
         return r
 
     def run_batch(self, items: list, *, tol: float = 0.0, connectivity: bool = False,
-                  sync: bool = True) -> list:
-        """Run many images in one batched call.  ``items`` holds dicts with
-        ``image``, ``S``, ``m``, ``iterations`` and optional preallocated
-        ``labels``/``centres``/``counts``/``residuals``."""
+                  sync: bool = True, graph: bool = True, autotune: bool = True) -> list:
+        """Run many images in one batched call (``sslic_run_batch``).
+
+        ``items`` holds dicts with ``image``, ``S``, ``m``, ``iterations`` and
+        optional preallocated ``labels``/``centres``/``counts``/``residuals``/
+        ``iters`` (device int32 [1]).  Returns one dict of outputs per item;
+        with ``sync`` also ``n_labels``.  Calling again with the same tensors
+        and options replays the captured graph."""
         n = len(items)
         descs = (ImageDesc * max(n, 1))()
         outs = []
@@ -214,6 +218,9 @@ class Context:
             res = itm.get("residuals")
             if res is None and itm.get("want_residuals"):
                 res = torch.zeros(int(itm["iterations"]), dtype=torch.float64, device=dev)
+            its = itm.get("iters")
+            if its is None:
+                its = torch.zeros(1, dtype=torch.int32, device=dev)
             d = descs[i]
             d.image = img.data_ptr()
             d.ndim = nd
@@ -228,8 +235,11 @@ class Context:
             d.centres = cen.data_ptr()
             d.counts = cnt.data_ptr()
             d.residuals = res.data_ptr() if res is not None else None
-            outs.append({"labels": lab, "centres": cen, "counts": cnt, "residuals": res})
-        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None)
+            d.iters_done = its.data_ptr()
+            outs.append({"labels": lab, "centres": cen, "counts": cnt, "residuals": res,
+                         "iters": its})
+        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None,
+                     0 if graph else 1, 0 if autotune else 1)
         nl = (ctypes.c_int32 * max(n, 1))()
         dev = items[0]["image"].device if n else self.device
         _check(lib().sslic_run_batch(self._h, descs, n, ctypes.byref(o), nl if sync else None,

@@ -91,6 +91,37 @@ def test_run_validates_before_any_device_work(lib):
     assert rc == -1 and "tol" in lib.sslic_last_error().decode()
 
 
+def test_run_batch_validates_before_any_device_work(lib):
+    """A batch with one invalid descriptor is refused with SSLIC_EINVAL, naming
+    the image, before any device work; an empty batch is a no-op."""
+    from paper_1806_08741_amd import sslic
+    dummy = ctypes.create_string_buffer(64)
+    ctxp = ctypes.cast(dummy, ctypes.c_void_p)
+    fake = 0x1000
+    o = sslic._Options(0.0, 1)
+    assert lib.sslic_run_batch(ctxp, None, 0, ctypes.byref(o), None, None) == 0
+    bad = [dict(channels=0), dict(dtype=5), dict(m=-1.0), dict(iterations=0), dict(image=None),
+           dict(centres=None), dict(ndim=5)]
+    for b in bad:
+        descs = (sslic.ImageDesc * 2)()
+        for i, d in enumerate(descs):
+            a = dict(image=fake, ndim=2, channels=3, dtype=0, m=10.0, iterations=3, labels=fake,
+                     centres=fake)
+            if i == 1:
+                a.update(b)
+            d.image, d.ndim, d.channels, d.dtype = a["image"], a["ndim"], a["channels"], a["dtype"]
+            d.m, d.iterations, d.labels, d.centres = a["m"], a["iterations"], a["labels"], a["centres"]
+            for ax in range(4):
+                d.dims[ax] = 64 if ax < 2 else 1
+                d.S[ax] = 16 if ax < 2 else 1
+        rc = lib.sslic_run_batch(ctxp, descs, 2, ctypes.byref(o), None, None)
+        assert rc == -1, b
+        assert "image 1" in lib.sslic_last_error().decode(), b
+    o.tol = -1.0
+    rc = lib.sslic_run_batch(ctxp, (sslic.ImageDesc * 1)(), 1, ctypes.byref(o), None, None)
+    assert rc == -1 and "tol" in lib.sslic_last_error().decode()
+
+
 def test_no_cpu_fallback_without_gpu(lib):
     """Without a GPU the library reports a device error instead of computing."""
     import torch
