@@ -58,6 +58,80 @@ def cpu_baseline(img_gpu, w, crop):
     return vox * w.iterations / dt / 1e6, dt, f"top-left {crop}x{crop} crop, {w.iterations} iterations"
 
 
+def bench_batch(args, n_images):
+    """The batched workload: n images of the batch recipe (half 2D RGB uint8,
+    half 3D float32, uneven sizes, per-image S and m, 10 iterations), timed as
+    whole sslic_run_batch calls (graph replays after the first) against the
+    same images run one at a time with sslic_run on one stream."""
+    import numpy as np
+    import torch
+    from paper_1806_08741_amd import sslic, synth
+
+    specs = synth.batch_specs(n_images)
+    print(f"[bench] generating {n_images} images", file=sys.stderr, flush=True)
+    items = [dict(image=synth.batch_image(sp, "cuda"), S=sp.S, m=sp.m, iterations=sp.iterations)
+             for sp in specs]
+    torch.cuda.synchronize()
+    vox = sum(sp.voxels for sp in specs)
+    work = sum(sp.voxels * sp.iterations for sp in specs)
+    ctx = sslic.Context(0)
+    outs = ctx.run_batch(items, graph=True)  # autotune + capture
+    items_o = [dict(it, labels=o["labels"], centres=o["centres"], counts=o["counts"],
+                    iters=o["iters"]) for it, o in zip(items, outs)]
+    for _ in range(args.warmup):
+        ctx.run_batch(items_o, graph=True, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.run_batch(items_o, graph=True, sync=False)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] batched: {dt_b * 1e3:.3f} ms per batch", file=sys.stderr, flush=True)
+
+    solo = [dict(labels=torch.empty_like(o["labels"]), centres=torch.empty_like(o["centres"]),
+                 counts=torch.empty_like(o["counts"])) for o in outs]
+
+    def one_at_a_time():
+        for it, so in zip(items, solo):
+            ctx.run(it["image"], it["S"], it["m"], it["iterations"], connectivity=False, out=so,
+                    sync=False)
+
+    for _ in range(args.warmup):
+        one_at_a_time()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_at_a_time()
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] one at a time: {dt_s * 1e3:.3f} ms per batch", file=sys.stderr, flush=True)
+    # equal results (integer images bit-identical, float images to 1e-4 of labels)
+    worst = 0.0
+    for sp, o, so in zip(specs, outs, solo):
+        d = float((o["labels"] != so["labels"]).float().mean().item())
+        if sp.dtype != torch.float32:
+            assert d == 0.0 and torch.equal(o["centres"], so["centres"])
+        worst = max(worst, d)
+    assert worst <= 1e-4, worst
+    rec = {
+        "metric": "SLIC Mvoxel*iter/s (whole batch per step; inputs resident in HBM)",
+        "value": round(work / dt_b / 1e6, 1),
+        "unit": "Mvoxel*iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt_b * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch-{n_images}", "images": n_images, "voxels": vox,
+                   "recipe": "half 2D RGB u8 sides log-uniform [96,1024], half 3D 1-channel f32 "
+                             "sides log-uniform [32,160]; S in {8,12,16}, m in {10,20}; "
+                             "Voronoi regions, noise sigma 8; 10 iterations, no connectivity"},
+        "one_at_a_time": {"value": round(work / dt_s / 1e6, 1), "ms_per_step": round(dt_s * 1e3, 4),
+                          "speedup_of_batch": round(dt_s / dt_b, 3)},
+        "label_disagreement_max": worst,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +152,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload.startswith("batch-"):
+        return bench_batch(args, int(args.workload.split("-")[1]))
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
