@@ -62,6 +62,7 @@ def _load():
         lib.or_grid_labels.argtypes = [I, P, P, P]
         lib.or_seed.argtypes = [P, I, P, I, I, P, P]
         lib.or_assign.argtypes = [P, I, P, I, I, P, D, P, I64, P]
+        lib.or_assign_points.argtypes = [P, I, P, I, I, P, D, P, I64, P, I64, P, P]
         lib.or_update.argtypes = [P, I, P, I, I, P, D, P, I64, P, P, P]
         lib.or_connectivity.argtypes = [I, P, P, P, I, I64, P, P]
         lib.or_run.argtypes = [P, I, P, I, I, P, D, I, D, I, P, P, P, P, P, P, P]
@@ -129,6 +130,22 @@ def assign(img, ndim, S, m, centres, labels):
     _check(_load().or_assign(_ptr(img), ndim, _ptr(dims), C, dt, _ptr(S), float(m),
                              _ptr(centres), centres.shape[0], _ptr(labels)))
     return labels
+
+
+def assign_points(img, ndim, S, m, centres, points):
+    """Labels (int32, -1 where no window holds the voxel) and least distances
+    of the voxels at linear indices ``points``, each computed on its own over
+    every centre."""
+    img, dims, C, dt = _geom(img, ndim)
+    S = np.asarray(S, dtype=np.int32)
+    centres = np.ascontiguousarray(centres, dtype=np.float64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    lab = np.empty(pts.shape[0], dtype=np.int32)
+    dist = np.empty(pts.shape[0], dtype=np.float64)
+    _check(_load().or_assign_points(_ptr(img), ndim, _ptr(dims), C, dt, _ptr(S), float(m),
+                                    _ptr(centres), centres.shape[0], _ptr(pts), pts.shape[0],
+                                    _ptr(lab), _ptr(dist)))
+    return lab, dist
 
 
 def update(img, ndim, S, m, labels, centres):

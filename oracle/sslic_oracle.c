@@ -313,6 +313,69 @@ int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
   return OR_OK;
 }
 
+/* Assignment of selected voxels one by one: the per-voxel reading of the same
+ * step (Sec. 2.1, Sec. 3.1 stage 2).  The label of x is the lowest k that
+ * attains the least D among the centres whose closed window holds x; every
+ * centre is examined for every point, in ascending k.
+ *   points     linear indices (axis 0 fastest), npts of them
+ *   labels_out -1 where no window holds the voxel
+ *   dist_out   the least D (INFINITY where none), or NULL */
+int or_assign_points(const void* img, int nd, const int64_t* dims, int C, int dtype,
+                     const int32_t* S, double m, const double* centres, int64_t K,
+                     const int64_t* points, int64_t npts, int32_t* labels_out,
+                     double* dist_out) {
+  img_t g;
+  int rc = make_img(&g, img, nd, dims, C, dtype);
+  if (rc) return rc;
+  if (!(m > 0.0) || K < 1 || npts < 0) return OR_EINVAL;
+  const int row = C + nd;
+  double w[OR_MAXD];
+  for (int i = 0; i < nd; ++i) w[i] = (m * m) / ((double)S[i] * (double)S[i]);
+  /* the window of every centre, as in or_assign */
+  int64_t* win = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)nd * (size_t)K);
+  if (!win) return OR_ENOMEM;
+  for (int64_t k = 0; k < K; ++k)
+    for (int i = 0; i < nd; ++i) {
+      double c = centres[k * row + C + i];
+      win[(k * nd + i) * 2] = (int64_t)ceil(c - (double)S[i]);
+      win[(k * nd + i) * 2 + 1] = (int64_t)floor(c + (double)S[i]);
+    }
+  int64_t x[OR_MAXD];
+  for (int64_t p = 0; p < npts; ++p) {
+    if (points[p] < 0 || points[p] >= g.N) {
+      free(win);
+      return OR_EINVAL;
+    }
+    coords_of(&g, points[p], x);
+    double best = INFINITY;
+    int32_t lab = -1;
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t* wk = win + k * nd * 2;
+      int inside = 1;
+      for (int i = 0; i < nd && inside; ++i) inside = wk[2 * i] <= x[i] && x[i] <= wk[2 * i + 1];
+      if (!inside) continue;
+      const double* ck = centres + k * row;
+      double D = 0.0;
+      for (int c = 0; c < C; ++c) {
+        double t = value_f(&g, points[p], c) - ck[c];
+        D = D + t * t;
+      }
+      for (int i = 0; i < nd; ++i) {
+        double t = (double)x[i] - ck[C + i];
+        D = D + w[i] * (t * t);
+      }
+      if (D < best) {
+        best = D;
+        lab = (int32_t)k;
+      }
+    }
+    labels_out[p] = lab;
+    if (dist_out) dist_out[p] = best;
+  }
+  free(win);
+  return OR_OK;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Update and residual (Sec. 2.2 / Sec. 3.1 stage 2: new centre = mean of
  * [I(x), x] over the voxels labelled k; Sec. 2.2 termination / Sec. 3.2:

@@ -27,6 +27,10 @@ int or_seed(const void* img, int nd, const int64_t* dims, int C, int dtype,
 int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
               const int32_t* S, double m, const double* centres, int64_t K,
               int32_t* labels);
+int or_assign_points(const void* img, int nd, const int64_t* dims, int C, int dtype,
+                     const int32_t* S, double m, const double* centres, int64_t K,
+                     const int64_t* points, int64_t npts, int32_t* labels_out,
+                     double* dist_out);
 int or_update(const void* img, int nd, const int64_t* dims, int C, int dtype,
               const int32_t* S, double m, const int32_t* labels, int64_t K,
               double* centres, int64_t* counts, double* residual);

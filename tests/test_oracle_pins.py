@@ -179,6 +179,34 @@ def test_p3_window_is_closed_and_uncovered_voxels_keep_labels():
     np.testing.assert_array_equal(lab, exp)
 
 
+@pytest.mark.parametrize("dims,S,m,C", [((40, 24), (8, 8), 8.0, 3), ((20, 16, 12), (4, 4, 4), 8.0, 1),
+                                        ((37, 29), (6, 5), 16.0, 2)])
+def test_p3c_assign_points_equals_windowed_brute_force(dims, S, m, C):
+    """Selected voxels, each assigned on its own: labels equal the windowed
+    argmin (first index on ties; -1 where no window reaches) and the reported
+    distance equals the FP64 distance to that centre."""
+    rng = np.random.default_rng(11)
+    n = len(dims)
+    N = int(np.prod(dims))
+    img = rng.integers(0, 256, size=tuple(dims[::-1]) + (C,)).astype(np.uint8)
+    K = 40
+    cen = np.zeros((K, C + n))
+    cen[:, :C] = rng.integers(0, 256, (K, C))
+    cen[:, C:] = rng.integers(0, np.array(dims), (K, n))  # integer: edges are hit exactly
+    cen[5] = cen[3]                                       # an exact tie
+    pts = np.unique(rng.integers(0, N, 300))
+    lab, dist = oracle.assign_points(img, n, S, m, cen, pts)
+    exp = brute.kmeans_assign(img, dims, S, m, cen, window=True, prev=np.full(N, -1))
+    np.testing.assert_array_equal(lab, exp[pts])
+    X = brute.coords(dims)[pts].astype(np.float64)
+    f = brute.features(img, dims)[pts]
+    w = (m / np.array(S, dtype=np.float64)) ** 2
+    ok = lab >= 0
+    d = ((f[ok] - cen[lab[ok], :C]) ** 2).sum(1) + (w * (X[ok] - cen[lab[ok], C:]) ** 2).sum(1)
+    np.testing.assert_allclose(dist[ok], d, rtol=1e-12)
+    assert np.all(np.isinf(dist[~ok]))
+
+
 # P3b: whole windowed run against brute force, integer image
 
 @pytest.mark.parametrize("dims,S,m,C", [((40, 24), (8, 8), 8.0, 3), ((20, 16, 12), (4, 4, 4), 8.0, 1),
