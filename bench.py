@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -45,17 +47,22 @@ def load_traffic(kernel: str, workload: str):
 
 
 def cpu_baseline(img_gpu, w, crop):
-    """The oracle as it stands, one thread, on the top-left crop x crop voxels
-    of the same image; returns (Mvoxel*iter/s, seconds, description)."""
-    import numpy as np
+    """The oracle as it stands, one thread, on the leading crop (side ``crop``
+    on every axis) of the same image; returns (Mvoxel*iter/s, seconds,
+    description)."""
     import oracle
-    sub = img_gpu[:crop, :crop].contiguous().cpu().numpy()
+    nd = len(w.dims)
+    sl = tuple(slice(0, min(crop, d)) for d in reversed(w.dims))
+    sub = img_gpu[sl].contiguous().cpu().numpy()
     t0 = time.perf_counter()
-    r = oracle.run(sub, 2, w.S, w.m, w.iterations, connectivity=w.connectivity)
+    r = oracle.run(sub, nd, w.S, w.m, w.iterations, connectivity=w.connectivity)
     dt = time.perf_counter() - t0
-    vox = sub.shape[0] * sub.shape[1]
+    vox = int(np.prod(sub.shape[:-1]))
     assert r["iterations"] == w.iterations
-    return vox * w.iterations / dt / 1e6, dt, f"top-left {crop}x{crop} crop, {w.iterations} iterations"
+    side = "x".join(str(min(crop, d)) for d in w.dims)
+    what = f"leading {side} crop, {w.iterations} iterations" + \
+        (" + connectivity" if w.connectivity else "")
+    return vox * w.iterations / dt / 1e6, dt, what
 
 
 def bench_batch(args, n_images):
@@ -208,8 +215,9 @@ def main():
     ap.add_argument("--requests", type=int, default=300, help="served workload: requests")
     ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="served workload: factor on every image side")
-    ap.add_argument("--cpu-crop", type=int, default=4096,
-                    help="side of the crop the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--cpu-crop", type=int, default=-1,
+                    help="side of the crop the CPU oracle is timed on (0 = skip; "
+                         "default 4096 in 2D, 224 in 3D)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -306,8 +314,9 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch},
         "kernels_ms": {k: round(v["ms_mean"], 4) for k, v in prof.items()},
     }
-    if args.cpu_crop > 0:
-        v, sec, desc = cpu_baseline(img, w, min(args.cpu_crop, w.dims[0]))
+    crop = args.cpu_crop if args.cpu_crop >= 0 else (4096 if len(w.dims) == 2 else 224)
+    if crop > 0:
+        v, sec, desc = cpu_baseline(img, w, crop)
         rec["cpu_baseline"] = {"value": round(v, 3), "unit": "Mvoxel*iter/s", "cores": 1,
                                "kind": "oracle", "sample": desc, "seconds": round(sec, 2)}
     print(json.dumps(rec), flush=True)
