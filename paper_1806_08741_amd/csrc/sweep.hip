@@ -288,10 +288,12 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
 
   // keeps the smaller (D, k) pair: the lowest cluster index among equal
   // distances; best starts at FLT_MAX, so +inf (outside the window) never wins
-  auto pick = [&](float D, int k, float& best, int& bk) {
-    const bool lt = (D < best) | ((D == best) & (k < bk));  // bitwise: no branches
-    best = lt ? D : best;
-    bk = lt ? k : bk;
+  // The best candidate so far is one 64-bit key: the bits of D (never
+  // negative, so they order as the values do) above the cluster index, so the
+  // smaller key is the smaller D and, among equal D, the lower index.
+  auto pick = [&](float D, int k, uint64_t& bkey) {
+    const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | (uint32_t)k;
+    bkey = key < bkey ? key : bkey;
   };
 
   // The meeting centres of a block, one at a time (their records are scalar
@@ -299,7 +301,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
   // whole block (mask mf) need no window test; for the others (mask mc) the
   // closed window is tested on every axis as one unsigned range compare.
   auto scan = [&](uint64_t mf, uint64_t mc, int jo, const int* x, const float* xs,
-                  const float* I, float& best, int& bk) {
+                  const float* I, uint64_t& bkey) {
     constexpr int RF = CM + ND + 1;  // mu, c', k
     while (mf) {
       const int l = (int)__builtin_ctzll(mf);
@@ -321,7 +323,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
       const int k = CC > 0 ? __float_as_int(R[rec_k(CC, ND)])
                            : reinterpret_cast<const int*>(rec)[rec_k(C, ND)];
-      pick(D, k, best, bk);
+      pick(D, k, bkey);
     }
     while (mc) {
       const int l = (int)__builtin_ctzll(mc);
@@ -349,7 +351,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         ok &= (uint32_t)(x[i] - lo) <= (uint32_t)(hi - lo);
       }
       D = ok ? D : __builtin_inff();
-      pick(D, Ri[rec_k(C, ND)], best, bk);
+      pick(D, Ri[rec_k(C, ND)], bkey);
     }
   };
 
@@ -435,12 +437,13 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       float I[CM];
       for (int c = 0; c < C; ++c) I[c] = (float)img[vl * C + c];
 
-      float best = 3.402823466e38f;  // FLT_MAX: out-of-window distances (+inf) never win or tie
-      int bk = -1;
+      // no candidate yet: FLT_MAX; out-of-window distances (+inf) never win
+      constexpr uint64_t kNone = (uint64_t)0x7f7fffffu << 32 | 0xffffffffu;
+      uint64_t bkey = kNone;
       if (rowfit) {
         uint64_t mf, mc;
         test(held, hlo, hhi, blo, bhi, mf, mc);
-        scan(mf, mc, hjo, x, xs, I, best, bk);
+        scan(mf, mc, hjo, x, xs, I, bkey);
       } else {
         int b0[ND], b1[ND];
         for (int i = 0; i < ND; ++i) {
@@ -459,7 +462,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
           }
           uint64_t mf, mc;
           test(bheld, lo, hi, blo, bhi, mf, mc);
-          scan(mf, mc, jl * RS * 4, x, xs, I, best, bk);
+          scan(mf, mc, jl * RS * 4, x, xs, I, bkey);
         } else {
           // more centres than lanes (a crowded neighbourhood): each lane walks them
           int rc[ND];
@@ -485,11 +488,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
                 const float t = I[c] - rec[c];
                 D = fmaf(t, t, D);
               }
-              const int k = irec2[rec_k(C, ND)];
-              if (D < best || (D == best && k < bk)) {
-                best = D;
-                bk = k;
-              }
+              pick(D, irec2[rec_k(C, ND)], bkey);
             }
             int i = 1;
             while (i < ND) {
@@ -501,6 +500,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
           }
         }
       }
+      int bk = bkey == kNone ? -1 : (int)(uint32_t)bkey;
       if (valid) {
         if (bk < 0) bk = first ? grid_label(g, x, ND) : a.labels[v];
         a.labels[v] = bk;
