@@ -278,9 +278,12 @@ def main():
           + ", ".join(f"{k} {v['ms_mean']:.3f} ms" for k, v in prof.items()),
           file=sys.stderr, flush=True)
 
-    # sanity: the timed result is a labelling of the whole image
+    # sanity: the timed result is a labelling of the whole image (connectivity
+    # adds labels K, K+1, ...)
     lab = out["labels"]
-    assert int(lab.min()) >= 0 and int(lab.max()) < K
+    n_labels = ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity,
+                       out=out)["n_labels"]
+    assert int(lab.min()) >= 0 and int(lab.max()) < n_labels
 
     ms_step = dt / args.steps * 1e3
     value = N * w.iterations * args.steps / dt / 1e6

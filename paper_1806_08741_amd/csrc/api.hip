@@ -110,7 +110,8 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
     L.cc_size = put((size_t)g.N * 4);
     L.cc_final = put((size_t)g.N);
     L.cc_newlab = put((size_t)g.N * 4);
-    L.cc_part = put((size_t)(g.N / 4096 + 2) * 4);
+    L.cc_part = put((size_t)cc_part_ints(g.N) * 4);
+    L.cc_roots = put((size_t)g.N * 4);
   }
   L.total = o;
   return L;
@@ -153,14 +154,15 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L) {
   return it;
 }
 
-CCBuf cc_view(sslic_ctx* ctx, const Layout& L) {
+CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N) {
   CCBuf c;
   char* b = ctx->ws;
   c.parent = (int32_t*)(b + L.cc_parent);
   c.size = (int32_t*)(b + L.cc_size);
   c.final_ = (uint8_t*)(b + L.cc_final);
   c.newlab = (int32_t*)(b + L.cc_newlab);
-  c.part = (int32_t*)(b + L.cc_part);
+  cc_carve(c, (int32_t*)(b + L.cc_part), N);
+  c.roots = (int32_t*)(b + L.cc_roots);
   c.total = (int32_t*)(b + L.flags) + 2;  // flags: done, iters, total, n_labels
   return c;
 }
@@ -325,7 +327,7 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
   int32_t* nl = nlab_slot(ctx, L);
   if (cc) {
     Mark mk(ctx, "connectivity", s);
-    HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
+    HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L, g.N), nl, s));
   } else {
     HIP_TRY(launch_fill_i32(nl, (int32_t)g.K, 1, s));
   }
@@ -419,7 +421,7 @@ int sslic_connectivity(sslic_ctx* ctx, int ndim, const int64_t* dims, const int3
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   int32_t* nl = nlab_slot(ctx, L);
-  HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L), nl, s));
+  HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L, g.N), nl, s));
   if (n_labels_dev) HIP_TRY(hipMemcpyAsync(n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
   return read_ints(ctx, s, nl, n_labels_out, nullptr, nullptr);
 }

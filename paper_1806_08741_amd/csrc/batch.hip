@@ -37,7 +37,7 @@ struct BLayout {
   size_t imgs, cl_img, tile_img, upload_bytes;
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, brec, scan_part;
   size_t acc, part, res, flags, nlab;
-  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, total;
+  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, cc_roots, total;
 };
 
 std::array<int, 7> key_of(const Geo& g) {
@@ -255,7 +255,8 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
     c.size = reinterpret_cast<int32_t*>(b + P.L.cc_size);
     c.final_ = reinterpret_cast<uint8_t*>(b + P.L.cc_final);
     c.newlab = reinterpret_cast<int32_t*>(b + P.L.cc_newlab);
-    c.part = reinterpret_cast<int32_t*>(b + P.L.cc_part);
+    cc_carve(c, reinterpret_cast<int32_t*>(b + P.L.cc_part), P.Nmax);
+    c.roots = reinterpret_cast<int32_t*>(b + P.L.cc_roots);
     c.total = flags + 2 * P.n + 1;
     int32_t* nlab = reinterpret_cast<int32_t*>(b + P.L.nlab);
     for (int j = 0; j < P.n; ++j) {
@@ -409,7 +410,8 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       L.cc_size = put((size_t)P.Nmax * 4);
       L.cc_final = put((size_t)P.Nmax);
       L.cc_newlab = put((size_t)P.Nmax * 4);
-      L.cc_part = put((size_t)(P.Nmax / 4096 + 2) * 4);
+      L.cc_part = put((size_t)cc_part_ints(P.Nmax) * 4);
+      L.cc_roots = put((size_t)P.Nmax * 4);
     }
     L.total = off;
     if ((rc = ensure_bws(ctx, L.total))) return rc;

@@ -57,12 +57,12 @@ size_t al(size_t v);
 // sections of the single-image workspace
 struct Layout {
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, brec, scan_part, acc, part, res_acc, flags;
-  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, total;
+  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, cc_roots, total;
 };
 Layout layout(const Geo& g, int iterations, bool cc, bool part);
 int ensure_ws(sslic_ctx* ctx, size_t need);
 Iter iter_view(sslic_ctx* ctx, const Layout& L);
-CCBuf cc_view(sslic_ctx* ctx, const Layout& L);
+CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N);
 int select_device(sslic_ctx* ctx);
 
 // the batched form behind sslic_run_batch (batch.hip)

@@ -167,9 +167,19 @@ struct CCBuf {
   int32_t* size;      // [N]
   uint8_t* final_;    // [N]
   int32_t* newlab;    // [N] label of each component root
-  int32_t* part;      // [ceil(N / 4096) + 1] block counts / offsets
+  int32_t* part;      // [ceil(N / 4096) + 1] large open roots per block, then offsets
+  int32_t* rpart;     // [ceil(N / 4096) + 1] roots per block, then offsets
+  int32_t* roots;     // [N] the roots in raster order
   int32_t* total;     // [1] number of new labels
+  int32_t* nroots;    // [1] number of roots
 };
+// ints the block counts of CCBuf take (part, rpart, nroots), and their carving
+inline int64_t cc_part_ints(int64_t N) { return 2 * (N / 4096 + 2) + 2; }
+inline void cc_carve(CCBuf& c, int32_t* region, int64_t N) {
+  c.part = region;
+  c.rpart = region + (N / 4096 + 2);
+  c.nroots = region + 2 * (N / 4096 + 2);
+}
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
                                const CCBuf& b, int32_t* n_labels_dev, hipStream_t s);
 
