@@ -121,14 +121,28 @@ __global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict
   seed_one<T>(g, img, cen, k);
 }
 
+// Calls f(descriptor) for the lanes with `in`.  A wave whose lanes all work
+// on one image (the common case: images hold many clusters) reads that
+// image's descriptor through scalar loads; a mixed wave reads it per lane.
+template <class F>
+__device__ __forceinline__ void with_image(const BImg* __restrict__ imgs, int im, bool in, F f) {
+  const int first = __builtin_amdgcn_readfirstlane(im);
+  if (__all(in && im == first)) {
+    f(imgs[first]);
+  } else if (in) {
+    f(imgs[im]);
+  }
+}
+
 // clusters [k0, k1) of a batch, all of one pixel type
 template <typename T>
 __global__ void seed_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ cl_img,
                                   int64_t k0, int64_t k1) {
-  int64_t gk = k0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (gk >= k1) return;
-  const BImg& d = imgs[cl_img[gk]];
-  seed_one<T>(d.g, reinterpret_cast<const T*>(d.img), d.cen, gk - d.koff);
+  const int64_t gk = k0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = gk < k1;
+  with_image(imgs, in ? cl_img[gk] : -1, in, [&](const BImg& d) {
+    seed_one<T>(d.g, reinterpret_cast<const T*>(d.img), d.cen, gk - d.koff);
+  });
 }
 
 __global__ void grid_labels_kernel(Geo g, int32_t* __restrict__ labels) {
@@ -207,12 +221,13 @@ __device__ __forceinline__ Iter batch_iter(const BImg& d, float* ctab, int32_t* 
 
 __global__ void prep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ cl_img,
                                   int64_t K, float* ctab, int32_t* bin_of, int32_t* bin_cnt) {
-  int64_t gk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (gk >= K) return;
-  const BImg& d = imgs[cl_img[gk]];
-  if (d.flags[0]) return;
-  const int64_t k = gk - d.koff;
-  prep_one(d.g, d.cen + k * d.g.row, k, batch_iter(d, ctab, bin_of, bin_cnt), d.binoff);
+  const int64_t gk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = gk < K;
+  with_image(imgs, in ? cl_img[gk] : -1, in, [&](const BImg& d) {
+    if (d.flags[0]) return;
+    const int64_t k = gk - d.koff;
+    prep_one(d.g, d.cen + k * d.g.row, k, batch_iter(d, ctab, bin_of, bin_cnt), d.binoff);
+  });
 }
 
 __global__ void prep_kernel(Geo g, const double* __restrict__ cen, Iter it) {
@@ -473,8 +488,7 @@ finalize_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__
   const bool in = gk < k1;
   const int im = in ? cl_img[gk] : -1;
   double e_sum = 0.0, e_cnt = 0.0;
-  if (in) {
-    const BImg& d = imgs[im];
+  with_image(imgs, im, in, [&](const BImg& d) {
     const bool next = t + 1 < d.iterations;
     if (!d.flags[0]) {
       const int64_t k = gk - d.koff;
@@ -483,7 +497,7 @@ finalize_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__
     }
     // an image that has stopped takes no part in later bin sorts
     if (d.flags[0] || !next) bin_of[gk] = -1;
-  }
+  });
   const int first = __builtin_amdgcn_readfirstlane(im);
   if (__all(im == first)) {
     e_sum = warp_sum(e_sum);

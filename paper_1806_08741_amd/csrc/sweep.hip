@@ -588,11 +588,12 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, brec, a, a.first, tile, s_keys, s_vals);
 }
 
-// Persistent form over the flat tile work-list of a group of images (same
-// pixel type, dimensionality, channel count and tile shape).  The list is cut
-// into 8 contiguous chunks, one per XCD (workgroups are dealt to XCDs round
+// The sweep over the flat tile work-list of a group of images (same pixel
+// type, dimensionality, channel count and tile shape).  The list is cut into
+// 8 contiguous chunks, one per XCD (workgroups are dealt to XCDs round
 // robin), so neighbouring tiles of an image share an L2; the workgroups of an
-// XCD stride through its chunk.  Tiles of converged images are skipped.
+// XCD stride through its chunk (one tile each when the grid has a workgroup
+// per tile).  Tiles of converged images are skipped.
 template <typename T, int ND, int CC, class SH>
 __global__ void __launch_bounds__(kThreads)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
