@@ -103,7 +103,7 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   L.scan_part = put((size_t)(g.nbins / 4096 + 2) * 4);
   L.acc = put((size_t)g.K * g.F * 8);
   L.part = put(part ? (size_t)g.K * ((size_t)1 << g.nd) * g.F * 8 : 0);
-  L.res_acc = put((size_t)2 * (iterations > 0 ? iterations : 1) * 8);
+  L.res_acc = put((size_t)2 * kResSlots * (iterations > 0 ? iterations : 1) * 8);
   L.flags = put(64);
   if (cc) {
     L.cc_parent = put((size_t)g.N * 4);
@@ -222,7 +222,7 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
   if (slots) HIP_TRY(launch_fill_u64(it.part, 0, g.K * ((int64_t)1 << g.nd) * g.F, s));
-  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * iterations, s));
+  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * kResSlots * iterations, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
   HIP_TRY(launch_prep(g, cen, it, s));
@@ -400,7 +400,7 @@ int sslic_update(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   hipStream_t s = (hipStream_t)stream;
   Iter it = iter_view(ctx, L);
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
-  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2, s));
+  HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * kResSlots, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_update(g, image, labels, it, s));
   HIP_TRY(launch_finalize(g, centres, counts, it, 0, 0, 0, s));

@@ -376,7 +376,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       b.a.bstart = nullptr;
       acc_w += (size_t)g.K * g.F;  // offsets in words, resolved below
       part_w += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * g.F : 0;
-      res_w += 2 * (size_t)images[i].iterations;
+      res_w += 2 * (size_t)kResSlots * images[i].iterations;
       Group& gr = P.groups.back();
       gr.i1 = j + 1;
       gr.k1 = P.K;
@@ -435,7 +435,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       b.a.done = b.flags;
       ao += (size_t)g.K * g.F;
       po += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * g.F : 0;
-      ro += 2 * (size_t)b.iterations;
+      ro += 2 * (size_t)kResSlots * b.iterations;
     }
     // upload descriptors and the cluster / tile -> image maps
     if ((rc = ensure_stage(ctx, L.upload_bytes))) return rc;

@@ -462,15 +462,20 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
       c += sh_n[i];
     }
     if (c > 0.0) {
-      atomicAdd(&it.res_acc[2 * t], s);
-      atomicAdd(&it.res_acc[2 * t + 1], c);
+      double* r = it.res_acc + 2 * ((int64_t)t * kResSlots + blockIdx.x % kResSlots);
+      atomicAdd(r, s);
+      atomicAdd(r + 1, c);
     }
   }
 }
 
 __global__ void residual_finish_kernel(Iter it, int t, double tol, double* residuals) {
   if (*it.done) return;
-  double s = it.res_acc[2 * t], c = it.res_acc[2 * t + 1];
+  double s = 0.0, c = 0.0;
+  for (int q = 0; q < kResSlots; ++q) {
+    s += it.res_acc[2 * (t * kResSlots + q)];
+    c += it.res_acc[2 * (t * kResSlots + q) + 1];
+  }
   double e = c > 0.0 ? s / c : 0.0;
   if (residuals) residuals[t] = e;
   *it.iters = t + 1;
@@ -498,17 +503,47 @@ finalize_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__
     // an image that has stopped takes no part in later bin sorts
     if (d.flags[0] || !next) bin_of[gk] = -1;
   });
+  // residual partials: summed per wave when the wave is one image, then per
+  // workgroup over its waves of one image, into slot blockIdx mod kResSlots
+  __shared__ double sh_s[kThreads / 64], sh_c[kThreads / 64];
+  __shared__ int sh_im[kThreads / 64];
   const int first = __builtin_amdgcn_readfirstlane(im);
-  if (__all(im == first)) {
+  const bool uni = __all(im == first);
+  const int slot = (int)(blockIdx.x % kResSlots);
+  if (uni) {
     e_sum = warp_sum(e_sum);
     e_cnt = warp_sum(e_cnt);
-    if (threadIdx.x % 64 == 0 && first >= 0 && e_cnt > 0.0) {
-      atomicAdd(&imgs[first].res[2 * t], e_sum);
-      atomicAdd(&imgs[first].res[2 * t + 1], e_cnt);
-    }
   } else if (in && e_cnt > 0.0) {
-    atomicAdd(&imgs[im].res[2 * t], e_sum);
-    atomicAdd(&imgs[im].res[2 * t + 1], e_cnt);
+    double* r = imgs[im].res + 2 * ((int64_t)t * kResSlots + slot);
+    atomicAdd(r, e_sum);
+    atomicAdd(r + 1, e_cnt);
+  }
+  const int wv = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) {
+    sh_im[wv] = uni ? first : -1;
+    sh_s[wv] = e_sum;
+    sh_c[wv] = e_cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cur = -1;
+    double s = 0.0, c = 0.0;
+    for (int w = 0; w <= kThreads / 64; ++w) {
+      const int i = w < kThreads / 64 ? sh_im[w] : -2;
+      if (i != cur) {
+        if (cur >= 0 && c > 0.0) {
+          double* r = imgs[cur].res + 2 * ((int64_t)t * kResSlots + slot);
+          atomicAdd(r, s);
+          atomicAdd(r + 1, c);
+        }
+        cur = i;
+        s = c = 0.0;
+      }
+      if (i >= 0) {
+        s += sh_s[w];
+        c += sh_c[w];
+      }
+    }
   }
 }
 
@@ -519,7 +554,11 @@ __global__ void residual_finish_batch_kernel(const BImg* __restrict__ imgs, int 
   if (i >= n) return;
   const BImg& d = imgs[i];
   if (d.flags[0]) return;
-  const double s = d.res[2 * t], c = d.res[2 * t + 1];
+  double s = 0.0, c = 0.0;
+  for (int q = 0; q < kResSlots; ++q) {
+    s += d.res[2 * (t * kResSlots + q)];
+    c += d.res[2 * (t * kResSlots + q) + 1];
+  }
   const double e = c > 0.0 ? s / c : 0.0;
   if (d.residuals) d.residuals[t] = e;
   d.flags[1] = t + 1;

@@ -65,10 +65,15 @@ struct Iter {
   int32_t* scan_part; // [ceil(nbins / 4096) + 1]
   uint64_t* acc;      // [K][F]    zero between uses (atomic sums)
   uint64_t* part;     // [K][2^nd][F] per-tile sums from the sweep; zero between uses
-  double* res_acc;    // [2 * iterations]  (sum, count) per iteration
+  double* res_acc;    // [iterations][kResSlots][2]  (sum, count) partials per iteration
   int32_t* done;      // converged flag: kernels return early when set
   int32_t* iters;     // iterations run
 };
+
+// Residual partials of one iteration are spread over this many (sum, count)
+// pairs (workgroup b adds into pair b mod kResSlots), so that the FP64 atomic
+// adds of the reduce step do not all meet at one address.
+constexpr int kResSlots = 16;
 
 // ---- launchers (each returns the hipError_t of its launches) -------------
 
@@ -120,7 +125,7 @@ struct BImg {
   int64_t* counts;        // caller's [K] or null
   double* residuals;      // caller's [iterations] or null
   int32_t* iters_out;     // caller's device int32 or null
-  double* res;            // [iterations][2] residual partials
+  double* res;            // [iterations][kResSlots][2] residual partials
   int32_t* flags;         // [0] done, [1] iterations run
   int64_t koff;           // first global cluster
   int64_t binoff;         // first global bin
