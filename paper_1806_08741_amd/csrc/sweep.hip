@@ -411,9 +411,25 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
     }
 
+    // This lane's voxel in block 0 of the row; block bx is B_0 * bx voxels
+    // further along axis 0.  Lanes outside the image read (and never write)
+    // the first voxel of their block.
+    int x[ND];
+    float xs[ND];
+    bool rowok = true;
+    for (int i = 1; i < ND; ++i) {
+      x[i] = rlo[i] + lx[i];
+      rowok = rowok && x[i] <= rhi[i];
+      xs[i] = (float)x[i] * g.sw[i];
+    }
+    int64_t vrow = to[0];
+    for (int i = 1; i < ND; ++i) vrow += (int64_t)(rowok ? x[i] : rlo[i]) * g.st[i];
+    const int lx0 = rowok ? lx[0] : 0;
+    const T* prow = img + (vrow + lx0) * C;
+    int32_t* lrow = a.labels + vrow + lx0;
+
     for (int bx = 0; bx < BX; ++bx) {
-      int blo[ND], bhi[ND], x[ND];
-      bool valid = true;
+      int blo[ND], bhi[ND];
       blo[0] = to[0] + bx * SS::B[0];
       if (blo[0] >= g.n[0]) break;
       bhi[0] = min(blo[0] + SS::B[0], g.n[0]) - 1;
@@ -421,21 +437,15 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         blo[i] = rlo[i];
         bhi[i] = rhi[i];
       }
-      for (int i = 0; i < ND; ++i) {
-        x[i] = blo[i] + lx[i];
-        valid = valid && x[i] <= bhi[i];
-      }
-      int64_t v = 0, v0 = 0;
-      float xs[ND];
-      for (int i = 0; i < ND; ++i) {
-        v += (int64_t)x[i] * g.st[i];
-        v0 += (int64_t)blo[i] * g.st[i];
-        xs[i] = (float)x[i] * g.sw[i];
-      }
-      // unconditional loads (lanes outside the image read the block's corner)
-      const int64_t vl = valid ? v : v0;
+      x[0] = blo[0] + lx[0];
+      const bool okx = x[0] <= bhi[0];
+      const bool valid = rowok && okx;
+      xs[0] = (float)x[0] * g.sw[0];
+      const int step = bx * SS::B[0] - (okx ? 0 : lx0);
+      const T* px = prow + (int64_t)step * C;
+      int32_t* lp = lrow + step;
       float I[CM];
-      for (int c = 0; c < C; ++c) I[c] = (float)img[vl * C + c];
+      for (int c = 0; c < C; ++c) I[c] = (float)px[c];
 
       // no candidate yet: FLT_MAX; out-of-window distances (+inf) never win
       constexpr uint64_t kNone = (uint64_t)0x7f7fffffu << 32 | 0xffffffffu;
@@ -502,8 +512,8 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
       int bk = bkey == kNone ? -1 : (int)(uint32_t)bkey;
       if (valid) {
-        if (bk < 0) bk = first ? grid_label(g, x, ND) : a.labels[v];
-        a.labels[v] = bk;
+        if (bk < 0) bk = first ? grid_label(g, x, ND) : *lp;
+        *lp = bk;
         if constexpr (ACC) {
           if (bk != cur) {
             flush();
