@@ -99,7 +99,6 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   L.bin_cnt = put((size_t)g.nbins * 4);
   L.bin_start = put((size_t)(g.nbins + 1) * 4);
   L.bin_items = put((size_t)g.K * 4);
-  L.brec = put((size_t)g.K * g.rs * 4);
   L.scan_part = put((size_t)(g.nbins / 4096 + 2) * 4);
   L.acc = put((size_t)g.K * g.F * 8);
   L.part = put(part ? (size_t)g.K * ((size_t)1 << g.nd) * g.F * 8 : 0);
@@ -144,7 +143,6 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L) {
   it.bin_cnt = (int32_t*)(b + L.bin_cnt);
   it.bin_start = (int32_t*)(b + L.bin_start);
   it.bin_items = (int32_t*)(b + L.bin_items);
-  it.brec = (float*)(b + L.brec);
   it.scan_part = (int32_t*)(b + L.scan_part);
   it.acc = (uint64_t*)(b + L.acc);
   it.part = (uint64_t*)(b + L.part);

@@ -35,7 +35,7 @@ struct Group {
 // so that one copy uploads them
 struct BLayout {
   size_t imgs, cl_img, tile_img, upload_bytes;
-  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, brec, scan_part;
+  size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part;
   size_t acc, part, res, flags, nlab;
   size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, cc_roots, total;
 };
@@ -164,7 +164,7 @@ int autotune(sslic_ctx* ctx, const sslic_image_desc& d, const Geo& g, hipStream_
       if (r == 1) e = hipEventRecord(e0, s);
       if (e == hipSuccess)
         e = launch_sweep_batch(g.dtype, g.nd, g.C, v, dimg, dtile, 0, b.a.ntiles, it.bin_start,
-                               it.brec, 1, grid, s);
+                               it.bin_items, it.ctab, 1, grid, s);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -210,7 +210,6 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
   it.bin_cnt = reinterpret_cast<int32_t*>(b + P.L.bin_cnt);
   it.bin_start = reinterpret_cast<int32_t*>(b + P.L.bin_start);
   it.bin_items = reinterpret_cast<int32_t*>(b + P.L.bin_items);
-  it.brec = reinterpret_cast<float*>(b + P.L.brec);
   it.scan_part = reinterpret_cast<int32_t*>(b + P.L.scan_part);
   it.done = flags + 2 * P.n;  // the bin sort runs every iteration
   Geo gb;
@@ -244,7 +243,7 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
       // several tiles per workgroup)
       const unsigned grid = (unsigned)g.ntiles;
       HIP_TRY(launch_sweep_batch(g.dtype, g.nd, g.C, g.var, imgs, tile_img, g.tile0, g.ntiles,
-                                 it.bin_start, it.brec, t == 0, grid, q));
+                                 it.bin_start, it.bin_items, it.ctab, t == 0, grid, q));
     }
     for (const Group& g : P.groups)
       HIP_TRY(launch_finalize_batch(g.dtype, g.nd, g.C, imgs, cl_img, g.k0, g.k1, ctab, it.bin_of,
@@ -401,7 +400,6 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
     L.bin_cnt = put((size_t)P.nbins * 4);
     L.bin_start = put((size_t)(P.nbins + 1) * 4);
     L.bin_items = put((size_t)P.K * 4);
-    L.brec = put((size_t)P.K * P.rs * 4);
     L.scan_part = put((size_t)(P.nbins / 4096 + 2) * 4);
     L.acc = put(acc_w * 8);
     L.part = put(part_w * 8);
@@ -426,7 +424,6 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
     for (int j = 0; j < n; ++j) {
       BImg& b = bi[j];
       const Geo& g = b.g;
-      b.a.brec = reinterpret_cast<const float*>(base + L.brec);
       b.a.ctab = reinterpret_cast<const float*>(base + L.ctab) + b.koff * P.rs;
       b.a.acc = reinterpret_cast<uint64_t*>(base + L.acc) + ao;
       b.a.part = b.a.slots ? reinterpret_cast<uint64_t*>(base + L.part) + po : nullptr;

@@ -336,16 +336,6 @@ __global__ void binsort_kernel(Geo g, Iter it) {
   it.bin_cnt[b] = 0;
 }
 
-// Records in bin order, so that a bin's centres are read contiguously.
-__global__ void binrec_kernel(Geo g, Iter it) {
-  if (*it.done) return;
-  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= g.K) return;
-  const float4* src = reinterpret_cast<const float4*>(it.ctab + (int64_t)it.bin_items[j] * g.rs);
-  float4* dst = reinterpret_cast<float4*>(it.brec + j * g.rs);
-  for (int q = 0; q < g.rs / 4; ++q) dst[q] = src[q];
-}
-
 // ---------------------------------------------------------------------------
 // Update, final step: sums / count in FP64 (correctly rounded, as the oracle),
 // the residual term of the cluster, counts out, accumulators reset, and the
@@ -613,7 +603,6 @@ hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s) {
   scan_add_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(it.bin_start, it.scan_part, g.nbins, it.done);
   scatter_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, it);
   binsort_kernel<<<blocks_for(g.nbins), kThreads, 0, s>>>(g, it);
-  binrec_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, it);
   return hipGetLastError();
 }
 

@@ -61,7 +61,6 @@ struct Iter {
   int32_t* bin_cnt;   // [nbins]   counts, then cursors; zero between uses
   int32_t* bin_start; // [nbins + 1]
   int32_t* bin_items; // [K]     cluster indices in bin order (ascending within a bin)
-  float* brec;        // [K][rs]  their records, in the same order
   int32_t* scan_part; // [ceil(nbins / 4096) + 1]
   uint64_t* acc;      // [K][F]    zero between uses (atomic sums)
   uint64_t* part;     // [K][2^nd][F] per-tile sums from the sweep; zero between uses
@@ -86,13 +85,15 @@ hipError_t launch_grid_labels(const Geo& g, int32_t* labels, hipStream_t s);
 
 // f64 centres -> assignment table + bin of every cluster + bin counts
 hipError_t launch_prep(const Geo& g, const double* cen, const Iter& it, hipStream_t s);
-// bin counts -> CSR (bin_start, bin_items sorted by cluster index)
+// bin counts -> CSR (bin_start, bin_items sorted by cluster index); the sweep
+// reads a bin's records through bin_items
 hipError_t launch_bins(const Geo& g, const Iter& it, hipStream_t s);
 
 // Arguments of the fused assignment + map sweep (sweep.hip).
 struct SweepArgs {
   const int32_t* bstart;
-  const float* brec;
+  const int32_t* items;   // cluster index at every bin position (bin order)
+  const float* recs;      // records, by cluster index
   const float* ctab;
   int32_t* labels;
   int first;
@@ -137,7 +138,8 @@ struct BImg {
 // sweep of one group's tiles (persistent; grid = workgroups)
 hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
                               const int32_t* tile_img, int tile0, int ntiles,
-                              const int32_t* bin_start, const float* brec, int first,
+                              const int32_t* bin_start, const int32_t* items, const float* recs,
+                              int first,
                               unsigned grid, hipStream_t s);
 // seeding of the clusters [k0, k1) of one pixel type (cluster -> image map cl_img)
 hipError_t launch_seed_batch(int dtype, const BImg* imgs, const int32_t* cl_img, int64_t k0,

@@ -163,7 +163,8 @@ struct RunSum<true> {
 template <typename T, int ND, int CC, bool ACC, class SH>
 __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ img,
                                            const int32_t* __restrict__ bstart,
-                                           const float* __restrict__ brec, const SweepArgs& a,
+                                           const int32_t* __restrict__ items,
+                                           const float* __restrict__ recs, const SweepArgs& a,
                                            int first, int tile, int* s_keys, uint64_t* s_vals) {
   using SS = SH;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
@@ -307,7 +308,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       const int l = (int)__builtin_ctzll(mf);
       mf &= mf - 1;
       const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
-      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + o);
+      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(recs) + o);
       float R[RF];
 #pragma unroll
       for (int w = 0; w < RF; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
@@ -329,7 +330,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       const int l = (int)__builtin_ctzll(mc);
       mc &= mc - 1;
       const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
-      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(brec) + o);
+      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(recs) + o);
       float R[RN];
 #pragma unroll
       for (int w = 0; w < RN; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
@@ -358,14 +359,15 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
   // meets / covers test of the record held by this lane against a block box
   auto test = [&](bool held, const int* lo, const int* hi, const int* blo, const int* bhi,
                   uint64_t& mf, uint64_t& mc) {
-    bool meets = held, covers = true;
+    bool meets = held, covers = true;  // bitwise: the compares combine as masks
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      meets = meets && lo[i] <= bhi[i] && hi[i] >= blo[i];
-      covers = covers && lo[i] <= blo[i] && hi[i] >= bhi[i];
+      meets &= (lo[i] <= bhi[i]) & (hi[i] >= blo[i]);
+      covers &= (lo[i] <= blo[i]) & (hi[i] >= bhi[i]);
     }
-    mf = __ballot(meets && covers);
-    mc = __ballot(meets && !covers);
+    const uint64_t m = __ballot(meets), cv = __ballot(covers);
+    mf = m & cv;
+    mc = m & ~cv;
   };
 
   constexpr int BX = SS::T[0] / SS::B[0];            // blocks per row (axis 0)
@@ -401,9 +403,10 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
     const bool rowfit = nrec <= 64;
     const bool held = rowfit && lane < nrec;
     int hlo[ND], hhi[ND];
-    const int hjo = rjl * RS * 4;
+    const int rk = items[held ? rjl : 0];  // the record of the cluster at that bin position
+    const int hjo = rk * RS * 4;
     {
-      const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(held ? rjl : 0) * RS);
+      const int* irec = reinterpret_cast<const int*>(recs + (int64_t)rk * RS);
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
         hlo[i] = irec[rec_lo(C, ND) + i];
@@ -465,14 +468,15 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         if (cnt <= 64) {
           const bool bheld = lane < cnt;
           int lo[ND], hi[ND];
-          const int* irec = reinterpret_cast<const int*>(brec + (int64_t)(bheld ? jl : 0) * RS);
+          const int bk0 = items[bheld ? jl : 0];
+          const int* irec = reinterpret_cast<const int*>(recs + (int64_t)bk0 * RS);
           for (int i = 0; i < ND; ++i) {
             lo[i] = irec[rec_lo(C, ND) + i];
             hi[i] = irec[rec_hi(C, ND) + i];
           }
           uint64_t mf, mc;
           test(bheld, lo, hi, blo, bhi, mf, mc);
-          scan(mf, mc, jl * RS * 4, x, xs, I, bkey);
+          scan(mf, mc, bk0 * RS * 4, x, xs, I, bkey);
         } else {
           // more centres than lanes (a crowded neighbourhood): each lane walks them
           int rc[ND];
@@ -483,7 +487,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
             const int ja = bstart[bl];
             const int jb = bstart[bl + (b1[0] - b0[0]) + 1];
             for (int j = ja; j < jb; ++j) {
-              const float* rec = brec + (int64_t)j * RS;
+              const float* rec = recs + (int64_t)items[j] * RS;
               const int* irec2 = reinterpret_cast<const int*>(rec);
               bool ok = true;
               for (int i = 0; i < ND; ++i)
@@ -587,7 +591,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
 template <typename T, int ND, int CC, bool ACC>
 __global__ void __launch_bounds__(kThreads)
 sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
-             const float* __restrict__ brec, SweepArgs a) {
+             const int32_t* __restrict__ items, const float* __restrict__ recs, SweepArgs a) {
   if (*a.done) return;
   using SH = Shape<ND, 0>;
   __shared__ int s_keys[ACC ? SH::kHash : 1];
@@ -595,7 +599,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   const int per = (int)(gridDim.x / 8);
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (tile >= a.ntiles) return;
-  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, brec, a, a.first, tile, s_keys, s_vals);
+  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, items, recs, a, a.first, tile, s_keys, s_vals);
 }
 
 // The sweep over the flat tile work-list of a group of images (same pixel
@@ -608,7 +612,7 @@ template <typename T, int ND, int CC, class SH>
 __global__ void __launch_bounds__(kThreads)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
                    int ntiles, const int32_t* __restrict__ bin_start,
-                   const float* __restrict__ brec, int first) {
+                   const int32_t* __restrict__ items, const float* __restrict__ recs, int first) {
   __shared__ int s_keys[SH::kHash];
   __shared__ uint64_t s_vals[SH::kHash * entry_words<T, ND, CC, SH>()];
   const int xcd = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
@@ -619,7 +623,7 @@ sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ ti
     if (d.flags[0]) continue;
     __syncthreads();  // the previous tile's table is read out
     sweep_tile<T, ND, CC, true, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
-                                   brec, d.a, first, tile0 + t - d.tile_off, s_keys, s_vals);
+                                   items, recs, d.a, first, tile0 + t - d.tile_off, s_keys, s_vals);
   }
 }
 
@@ -638,10 +642,10 @@ hipError_t dispatch_c(const Geo& g, const void* img, SweepArgs a, hipStream_t s)
   const unsigned grid = (unsigned)(((int64_t)nt + 7) / 8 * 8);  // a multiple of the XCD count
   const T* p = (const T*)img;
   switch (g.C) {
-    case 1: sweep_kernel<T, ND, 1, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
-    case 3: sweep_kernel<T, ND, 3, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
-    case 4: sweep_kernel<T, ND, 4, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
-    default: sweep_kernel<T, ND, 0, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.brec, a); break;
+    case 1: sweep_kernel<T, ND, 1, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.items, a.recs, a); break;
+    case 3: sweep_kernel<T, ND, 3, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.items, a.recs, a); break;
+    case 4: sweep_kernel<T, ND, 4, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.items, a.recs, a); break;
+    default: sweep_kernel<T, ND, 0, ACC><<<grid, kThreads, 0, s>>>(g, p, a.bstart, a.items, a.recs, a); break;
   }
   return hipGetLastError();
 }
@@ -666,41 +670,41 @@ hipError_t dispatch(const Geo& g, const void* img, const SweepArgs& a, hipStream
 
 template <typename T, int ND, int CC, int VAR>
 hipError_t batch_launch(const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
-                        const int32_t* bin_start, const float* brec, int first, unsigned grid,
-                        hipStream_t s) {
+                        const int32_t* bin_start, const int32_t* items, const float* recs,
+                        int first, unsigned grid, hipStream_t s) {
   sweep_batch_kernel<T, ND, CC, Shape<ND, VAR>><<<grid, kThreads, 0, s>>>(
-      imgs, tile_img, tile0, ntiles, bin_start, brec, first);
+      imgs, tile_img, tile0, ntiles, bin_start, items, recs, first);
   return hipGetLastError();
 }
 
 template <typename T, int ND, int CC>
 hipError_t batch_var(int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
-                     const int32_t* bin_start, const float* brec, int first, unsigned grid,
+                     const int32_t* bin_start, const int32_t* items, const float* recs, int first, unsigned grid,
                      hipStream_t s) {
-  return var == 1 ? batch_launch<T, ND, CC, 1>(imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s)
-                  : batch_launch<T, ND, CC, 0>(imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+  return var == 1 ? batch_launch<T, ND, CC, 1>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s)
+                  : batch_launch<T, ND, CC, 0>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
 }
 
 template <typename T, int ND>
 hipError_t batch_c(int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
-                   const int32_t* bin_start, const float* brec, int first, unsigned grid,
+                   const int32_t* bin_start, const int32_t* items, const float* recs, int first, unsigned grid,
                    hipStream_t s) {
   switch (C) {
-    case 1: return batch_var<T, ND, 1>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    case 3: return batch_var<T, ND, 3>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    case 4: return batch_var<T, ND, 4>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    default: return batch_var<T, ND, 0>(var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case 1: return batch_var<T, ND, 1>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case 3: return batch_var<T, ND, 3>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case 4: return batch_var<T, ND, 4>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    default: return batch_var<T, ND, 0>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
   }
 }
 
 template <typename T>
 hipError_t batch_nd(int nd, int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0,
-                    int ntiles, const int32_t* bin_start, const float* brec, int first,
+                    int ntiles, const int32_t* bin_start, const int32_t* items, const float* recs, int first,
                     unsigned grid, hipStream_t s) {
   switch (nd) {
-    case 2: return batch_c<T, 2>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    case 3: return batch_c<T, 3>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    default: return batch_c<T, 4>(C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case 2: return batch_c<T, 2>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case 3: return batch_c<T, 3>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    default: return batch_c<T, 4>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
   }
 }
 
@@ -730,7 +734,8 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
   (void)var;  // the single-image path uses the default tile
   SweepArgs a{};
   a.bstart = it.bin_start;
-  a.brec = it.brec;
+  a.items = it.bin_items;
+  a.recs = it.ctab;
   a.ctab = it.ctab;
   a.labels = labels;
   a.first = first;
@@ -742,14 +747,14 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
 
 hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
                               const int32_t* tile_img, int tile0, int ntiles,
-                              const int32_t* bin_start, const float* brec, int first,
+                              const int32_t* bin_start, const int32_t* items, const float* recs, int first,
                               unsigned grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   grid = (grid + 7) / 8 * 8;
   switch (dtype) {
-    case kU8: return batch_nd<uint8_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    case kU16: return batch_nd<uint16_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
-    default: return batch_nd<float>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, brec, first, grid, s);
+    case kU8: return batch_nd<uint8_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case kU16: return batch_nd<uint16_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    default: return batch_nd<float>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
   }
 }
 
