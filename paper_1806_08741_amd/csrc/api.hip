@@ -101,7 +101,8 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   L.bin_items = put((size_t)g.K * 4);
   L.scan_part = put((size_t)(g.nbins / 4096 + 2) * 4);
   L.acc = put((size_t)g.K * g.F * 8);
-  L.part = put(part ? (size_t)g.K * ((size_t)1 << g.nd) * g.F * 8 : 0);
+  L.accf = put((size_t)(g.K + 3) / 4 * 4);
+  L.part = put(part ? (size_t)g.K * ((size_t)1 << g.nd) * (g.F + 1) * 8 : 0);
   L.res_acc = put((size_t)2 * kResSlots * (iterations > 0 ? iterations : 1) * 8);
   L.flags = put(64);
   if (cc) {
@@ -145,6 +146,7 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L) {
   it.bin_items = (int32_t*)(b + L.bin_items);
   it.scan_part = (int32_t*)(b + L.scan_part);
   it.acc = (uint64_t*)(b + L.acc);
+  it.accf = (uint8_t*)(b + L.accf);
   it.part = (uint64_t*)(b + L.part);
   it.res_acc = (double*)(b + L.res_acc);
   it.done = (int32_t*)(b + L.flags);
@@ -219,7 +221,8 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   const int slots = sweep_slots(g);
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
-  if (slots) HIP_TRY(launch_fill_u64(it.part, 0, g.K * ((int64_t)1 << g.nd) * g.F, s));
+  HIP_TRY(launch_fill_i32((int32_t*)it.accf, 0, (g.K + 3) / 4, s));
+  if (slots) HIP_TRY(launch_fill_u64(it.part, 0, g.K * ((int64_t)1 << g.nd) * (g.F + 1), s));
   HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * kResSlots * iterations, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
@@ -231,7 +234,7 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
     }
     {
       Mark mk(ctx, "sweep", s);
-      HIP_TRY(launch_sweep(g, image, it, labels, t == 0, 1, s));
+      HIP_TRY(launch_sweep(g, image, it, labels, t, 1, s));
     }
     {
       Mark mk(ctx, "finalize", s);
@@ -380,7 +383,8 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_prep(g, centres, it, s));
   HIP_TRY(launch_bins(g, it, s));
-  HIP_TRY(launch_sweep(g, image, it, labels, 0, 0, s));
+  // as a later iteration: voxels outside every window keep the given label
+  HIP_TRY(launch_sweep(g, image, it, labels, 1, 0, s));
   return SSLIC_OK;
 }
 

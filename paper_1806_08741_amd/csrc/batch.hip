@@ -36,7 +36,7 @@ struct Group {
 struct BLayout {
   size_t imgs, cl_img, tile_img, upload_bytes;
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part;
-  size_t acc, part, res, flags, nlab;
+  size_t acc, accf, part, res, flags, nlab;
   size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, cc_roots, total;
 };
 
@@ -153,6 +153,7 @@ int autotune(sslic_ctx* ctx, const sslic_image_desc& d, const Geo& g, hipStream_
     b.a.done = it.done;
     b.a.part = it.part;
     b.a.acc = it.acc;
+    b.a.accf = it.accf;
     b.flags = it.done;
     if ((rc = ensure_stage(ctx, sizeof(BImg)))) break;
     memcpy(ctx->bstage, &b, sizeof b);
@@ -164,7 +165,7 @@ int autotune(sslic_ctx* ctx, const sslic_image_desc& d, const Geo& g, hipStream_
       if (r == 1) e = hipEventRecord(e0, s);
       if (e == hipSuccess)
         e = launch_sweep_batch(g.dtype, g.nd, g.C, v, dimg, dtile, 0, b.a.ntiles, it.bin_start,
-                               it.bin_items, it.ctab, 1, grid, s);
+                               it.bin_items, it.ctab, 0, grid, s);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -219,6 +220,7 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
   gb.rs = P.rs;
 
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, P.nbins, q));
+  // accumulators and their flags (adjacent)
   HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(b + P.L.acc), 0,
                           (int64_t)((P.L.part - P.L.acc) / 8), q));
   HIP_TRY(launch_fill_u64(reinterpret_cast<uint64_t*>(b + P.L.part), 0,
@@ -243,7 +245,7 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
       // several tiles per workgroup)
       const unsigned grid = (unsigned)g.ntiles;
       HIP_TRY(launch_sweep_batch(g.dtype, g.nd, g.C, g.var, imgs, tile_img, g.tile0, g.ntiles,
-                                 it.bin_start, it.bin_items, it.ctab, t == 0, grid, q));
+                                 it.bin_start, it.bin_items, it.ctab, t, grid, q));
     }
     for (const Group& g : P.groups)
       HIP_TRY(launch_finalize_batch(g.dtype, g.nd, g.C, imgs, cl_img, g.k0, g.k1, ctab, it.bin_of,
@@ -374,7 +376,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       P.Nmax = std::max(P.Nmax, g.N);
       b.a.bstart = nullptr;
       acc_w += (size_t)g.K * g.F;  // offsets in words, resolved below
-      part_w += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * g.F : 0;
+      part_w += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * (g.F + 1) : 0;
       res_w += 2 * (size_t)kResSlots * images[i].iterations;
       Group& gr = P.groups.back();
       gr.i1 = j + 1;
@@ -402,6 +404,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
     L.bin_items = put((size_t)P.K * 4);
     L.scan_part = put((size_t)(P.nbins / 4096 + 2) * 4);
     L.acc = put(acc_w * 8);
+    L.accf = put((size_t)P.K);
     L.part = put(part_w * 8);
     L.res = put(res_w * 8);
     L.flags = put(((size_t)2 * n + 2) * 4);
@@ -426,12 +429,13 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       const Geo& g = b.g;
       b.a.ctab = reinterpret_cast<const float*>(base + L.ctab) + b.koff * P.rs;
       b.a.acc = reinterpret_cast<uint64_t*>(base + L.acc) + ao;
+      b.a.accf = reinterpret_cast<uint8_t*>(base + L.accf) + b.koff;
       b.a.part = b.a.slots ? reinterpret_cast<uint64_t*>(base + L.part) + po : nullptr;
       b.res = reinterpret_cast<double*>(base + L.res) + ro;
       b.flags = flags + 2 * j;
       b.a.done = b.flags;
       ao += (size_t)g.K * g.F;
-      po += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * g.F : 0;
+      po += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * (g.F + 1) : 0;
       ro += 2 * (size_t)kResSlots * b.iterations;
     }
     // upload descriptors and the cluster / tile -> image maps

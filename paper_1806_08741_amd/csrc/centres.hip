@@ -212,6 +212,7 @@ __device__ __forceinline__ Iter batch_iter(const BImg& d, float* ctab, int32_t* 
   it.bin_of = bin_of + d.koff;
   it.bin_cnt = bin_cnt;
   it.acc = d.a.acc;
+  it.accf = d.a.accf;
   it.part = d.a.part;
   it.res_acc = d.res;
   it.done = d.flags;
@@ -346,31 +347,43 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
-// The reduce step of cluster k: accumulators (and, with use_part, the tile
-// slots of the tiles its window meets, as the sweep chose them) -> new centre
-// in FP64, count, residual term (e_sum, e_cnt); then the next iteration's
-// record and bin when prep_next.
+// The reduce step of cluster k at iteration t: accumulators (and, with
+// use_part, the tile slots of the tiles its window meets, as the sweep chose
+// them, that carry this iteration's tag) -> new centre in FP64, count,
+// residual term (e_sum, e_cnt); then the next iteration's record and bin when
+// prep_next.  With use_part the accumulators are read (and cleared) only where
+// the sweep flagged them; without it they are the only source.
 template <int ND, int CC, bool FLT>
 __device__ __forceinline__ void finalize_one(const Geo& g, double* __restrict__ cen,
                                              int64_t* __restrict__ counts, const Iter& it,
-                                             int64_t k, int prep_next, int use_part,
+                                             int64_t k, int t, int prep_next, int use_part,
                                              const int* tdT, int64_t binoff, double& e_sum,
                                              double& e_cnt) {
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   const int C = CC > 0 ? CC : g.C;
   const int F = 1 + ND + C;
 
-    uint64_t* a = it.acc + k * F;
     uint64_t si[1 + ND];
     uint64_t sc[CM];
     double sf[CM];
+    if (!use_part || it.accf[k]) {
+      uint64_t* a = it.acc + k * F;
 #pragma unroll
-    for (int f = 0; f < 1 + ND; ++f) si[f] = a[f];
-    for (int c = 0; c < C; ++c) {
-      sc[c] = a[1 + ND + c];
-      sf[c] = __longlong_as_double((long long)sc[c]);
+      for (int f = 0; f < 1 + ND; ++f) si[f] = a[f];
+      for (int c = 0; c < C; ++c) {
+        sc[c] = a[1 + ND + c];
+        sf[c] = __longlong_as_double((long long)sc[c]);
+      }
+      for (int f = 0; f < F; ++f) a[f] = 0;
+      if (use_part) it.accf[k] = 0;
+    } else {
+#pragma unroll
+      for (int f = 0; f < 1 + ND; ++f) si[f] = 0;
+      for (int c = 0; c < C; ++c) {
+        sc[c] = 0;
+        sf[c] = 0.0;
+      }
     }
-    for (int f = 0; f < F; ++f) a[f] = 0;
     if (use_part) {
       // the slots of the tiles this cluster's window meets (as the sweep chose them)
       const int32_t* irec = reinterpret_cast<const int32_t*>(it.ctab + k * g.rs);
@@ -392,7 +405,8 @@ __device__ __forceinline__ void finalize_one(const Geo& g, double* __restrict__ 
             if ((q >> i) & 1) meets = meets && (t0[i] + 1) * tdT[i] <= hi[i];
           }
           if (!meets) continue;
-          uint64_t* p = it.part + (k * (1 << ND) + q) * F;
+          const uint64_t* p = it.part + (k * (1 << ND) + q) * (F + 1);
+          if (p[F] != (uint64_t)(t + 1)) continue;  // not written this iteration
 #pragma unroll
           for (int f = 0; f < 1 + ND; ++f) si[f] += p[f];
           for (int c = 0; c < C; ++c) {
@@ -400,7 +414,6 @@ __device__ __forceinline__ void finalize_one(const Geo& g, double* __restrict__ 
             if (FLT) sf[c] += __longlong_as_double((long long)raw);
             else sc[c] += raw;
           }
-          for (int f = 0; f < F; ++f) p[f] = 0;
         }
       }
     }
@@ -436,7 +449,8 @@ finalize_kernel(Geo g, double* __restrict__ cen, int64_t* __restrict__ counts, I
   __shared__ double sh_e[kThreads / 64], sh_n[kThreads / 64];
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double e_sum = 0.0, e_cnt = 0.0;
-  if (k < g.K) finalize_one<ND, CC, FLT>(g, cen, counts, it, k, prep_next, use_part, td.T, 0, e_sum, e_cnt);
+  if (k < g.K)
+    finalize_one<ND, CC, FLT>(g, cen, counts, it, k, t, prep_next, use_part, td.T, 0, e_sum, e_cnt);
   e_sum = warp_sum(e_sum);
   e_cnt = warp_sum(e_cnt);
   int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
@@ -487,7 +501,7 @@ finalize_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__
     const bool next = t + 1 < d.iterations;
     if (!d.flags[0]) {
       const int64_t k = gk - d.koff;
-      finalize_one<ND, CC, FLT>(d.g, d.cen, d.counts, batch_iter(d, ctab, bin_of, bin_cnt), k,
+      finalize_one<ND, CC, FLT>(d.g, d.cen, d.counts, batch_iter(d, ctab, bin_of, bin_cnt), k, t,
                                 next, d.a.slots, d.tdim, d.binoff, e_sum, e_cnt);
     }
     // an image that has stopped takes no part in later bin sorts

@@ -63,7 +63,9 @@ struct Iter {
   int32_t* bin_items; // [K]     cluster indices in bin order (ascending within a bin)
   int32_t* scan_part; // [ceil(nbins / 4096) + 1]
   uint64_t* acc;      // [K][F]    zero between uses (atomic sums)
-  uint64_t* part;     // [K][2^nd][F] per-tile sums from the sweep; zero between uses
+  uint8_t* accf;      // [K]       1 where acc holds sums (the sweep's atomic path)
+  uint64_t* part;     // [K][2^nd][F + 1] per-tile sums from the sweep, tagged with
+                      // iteration + 1 (older tags are stale and ignored)
   double* res_acc;    // [iterations][kResSlots][2]  (sum, count) partials per iteration
   int32_t* done;      // converged flag: kernels return early when set
   int32_t* iters;     // iterations run
@@ -96,19 +98,22 @@ struct SweepArgs {
   const float* recs;      // records, by cluster index
   const float* ctab;
   int32_t* labels;
-  int first;
+  int iter;               // iteration (0: uncovered voxels take their grid cell)
   const int32_t* done;
-  uint64_t* part;
+  uint64_t* part;         // [K][2^n][F + 1] tile slots, word F = iteration + 1 that wrote it
   uint64_t* acc;
+  uint8_t* accf;          // [K] 1 where acc holds sums
   int ntiles;
   int nt[kMaxDim];
   int slots;  // 1: per-cluster tile slots; 0: tiles narrower than a window, atomics only
 };
-// assignment of every voxel (labels); with `accumulate`, also the per-cluster
-// sums into it.part (tile slots) / it.acc (atomics).  `var` picks the tile
+// assignment of every voxel (labels) at iteration `iter` (0: voxels outside
+// every window take their grid cell's label, else they keep theirs); with
+// `accumulate`, also the per-cluster sums into it.part (tile slots tagged
+// iter + 1) / it.acc (atomics, flagged in it.accf).  `var` picks the tile
 // shape (0 default, 1 small).
 hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels,
-                        int first, int accumulate, hipStream_t s, int var = 0);
+                        int iter, int accumulate, hipStream_t s, int var = 0);
 constexpr int kTileVars = 2;
 int sweep_slots(const Geo& g, int var = 0);          // whether the sweep uses tile slots
 void sweep_tile_shape(int nd, int* T, int var = 0);  // its tile extent per axis
@@ -120,7 +125,7 @@ void sweep_tile_shape(int nd, int* T, int var = 0);  // its tile extent per axis
 // partials and flags are the image's own.
 struct BImg {
   Geo g;
-  SweepArgs a;            // a.bstart unused (bin_start + binoff), a.first per launch
+  SweepArgs a;            // a.bstart unused (bin_start + binoff), a.iter per launch
   const void* img;
   double* cen;            // caller's [K][C + n]
   int64_t* counts;        // caller's [K] or null
@@ -135,11 +140,12 @@ struct BImg {
   double tol;
   int tdim[kMaxDim];      // tile extent of its group
 };
-// sweep of one group's tiles (persistent; grid = workgroups)
+// sweep of one group's tiles at iteration `iter` (grid = workgroups, each
+// taking tiles grid apart)
 hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
                               const int32_t* tile_img, int tile0, int ntiles,
                               const int32_t* bin_start, const int32_t* items, const float* recs,
-                              int first,
+                              int iter,
                               unsigned grid, hipStream_t s);
 // seeding of the clusters [k0, k1) of one pixel type (cluster -> image map cl_img)
 hipError_t launch_seed_batch(int dtype, const BImg* imgs, const int32_t* cl_img, int64_t k0,

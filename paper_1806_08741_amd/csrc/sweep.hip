@@ -165,7 +165,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
                                            const int32_t* __restrict__ bstart,
                                            const int32_t* __restrict__ items,
                                            const float* __restrict__ recs, const SweepArgs& a,
-                                           int first, int tile, int* s_keys, uint64_t* s_vals) {
+                                           int iter, int tile, int* s_keys, uint64_t* s_vals) {
   using SS = SH;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   constexpr int RN = CM + 3 * ND + 1;  // record words read
@@ -252,6 +252,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
 #pragma unroll
       for (int w = 0; w < NW; ++w) atomicAdd(vv + w, (unsigned long long)pw[w]);
     } else {  // table full: global accumulators (coordinates made absolute)
+      a.accf[cur] = 1;
       unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)cur * F);
       atomicAdd(gg, (unsigned long long)rcnt);
       for (int i = 0; i < ND; ++i)
@@ -516,7 +517,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
       int bk = bkey == kNone ? -1 : (int)(uint32_t)bkey;
       if (valid) {
-        if (bk < 0) bk = first ? grid_label(g, x, ND) : *lp;
+        if (bk < 0) bk = iter == 0 ? grid_label(g, x, ND) : *lp;
         *lp = bk;
         if constexpr (ACC) {
           if (bk != cur) {
@@ -573,10 +574,12 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         q |= d << i;
       }
     }
-    if (q >= 0) {
-      uint64_t* dst = a.part + ((int64_t)k * NS + q) * F;
+    if (q >= 0) {  // the slot, tagged with the iteration that wrote it
+      uint64_t* dst = a.part + ((int64_t)k * NS + q) * (F + 1);
       for (int f = 0; f < F; ++f) dst[f] = out[f];
+      dst[F] = (uint64_t)(iter + 1);
     } else {
+      a.accf[k] = 1;
       unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)k * F);
       for (int f = 0; f < 1 + ND; ++f) atomicAdd(gg + f, (unsigned long long)out[f]);
       for (int c = 0; c < C; ++c) {
@@ -599,7 +602,7 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   const int per = (int)(gridDim.x / 8);
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (tile >= a.ntiles) return;
-  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, items, recs, a, a.first, tile, s_keys, s_vals);
+  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, items, recs, a, a.iter, tile, s_keys, s_vals);
 }
 
 // The sweep over the flat tile work-list of a group of images (same pixel
@@ -612,7 +615,7 @@ template <typename T, int ND, int CC, class SH>
 __global__ void __launch_bounds__(kThreads)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
                    int ntiles, const int32_t* __restrict__ bin_start,
-                   const int32_t* __restrict__ items, const float* __restrict__ recs, int first) {
+                   const int32_t* __restrict__ items, const float* __restrict__ recs, int iter) {
   __shared__ int s_keys[SH::kHash];
   __shared__ uint64_t s_vals[SH::kHash * entry_words<T, ND, CC, SH>()];
   const int xcd = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
@@ -623,7 +626,7 @@ sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ ti
     if (d.flags[0]) continue;
     __syncthreads();  // the previous tile's table is read out
     sweep_tile<T, ND, CC, true, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
-                                   items, recs, d.a, first, tile0 + t - d.tile_off, s_keys, s_vals);
+                                   items, recs, d.a, iter, tile0 + t - d.tile_off, s_keys, s_vals);
   }
 }
 
@@ -671,40 +674,40 @@ hipError_t dispatch(const Geo& g, const void* img, const SweepArgs& a, hipStream
 template <typename T, int ND, int CC, int VAR>
 hipError_t batch_launch(const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
                         const int32_t* bin_start, const int32_t* items, const float* recs,
-                        int first, unsigned grid, hipStream_t s) {
+                        int iter, unsigned grid, hipStream_t s) {
   sweep_batch_kernel<T, ND, CC, Shape<ND, VAR>><<<grid, kThreads, 0, s>>>(
-      imgs, tile_img, tile0, ntiles, bin_start, items, recs, first);
+      imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter);
   return hipGetLastError();
 }
 
 template <typename T, int ND, int CC>
 hipError_t batch_var(int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
-                     const int32_t* bin_start, const int32_t* items, const float* recs, int first, unsigned grid,
+                     const int32_t* bin_start, const int32_t* items, const float* recs, int iter, unsigned grid,
                      hipStream_t s) {
-  return var == 1 ? batch_launch<T, ND, CC, 1>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s)
-                  : batch_launch<T, ND, CC, 0>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+  return var == 1 ? batch_launch<T, ND, CC, 1>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s)
+                  : batch_launch<T, ND, CC, 0>(imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
 }
 
 template <typename T, int ND>
 hipError_t batch_c(int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0, int ntiles,
-                   const int32_t* bin_start, const int32_t* items, const float* recs, int first, unsigned grid,
+                   const int32_t* bin_start, const int32_t* items, const float* recs, int iter, unsigned grid,
                    hipStream_t s) {
   switch (C) {
-    case 1: return batch_var<T, ND, 1>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    case 3: return batch_var<T, ND, 3>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    case 4: return batch_var<T, ND, 4>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    default: return batch_var<T, ND, 0>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case 1: return batch_var<T, ND, 1>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    case 3: return batch_var<T, ND, 3>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    case 4: return batch_var<T, ND, 4>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    default: return batch_var<T, ND, 0>(var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
   }
 }
 
 template <typename T>
 hipError_t batch_nd(int nd, int C, int var, const BImg* imgs, const int32_t* tile_img, int tile0,
-                    int ntiles, const int32_t* bin_start, const int32_t* items, const float* recs, int first,
+                    int ntiles, const int32_t* bin_start, const int32_t* items, const float* recs, int iter,
                     unsigned grid, hipStream_t s) {
   switch (nd) {
-    case 2: return batch_c<T, 2>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    case 3: return batch_c<T, 3>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    default: return batch_c<T, 4>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case 2: return batch_c<T, 2>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    case 3: return batch_c<T, 3>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    default: return batch_c<T, 4>(C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
   }
 }
 
@@ -729,7 +732,7 @@ int sweep_slots(const Geo& g, int var) {
   return 1;
 }
 
-hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels, int first,
+hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels, int iter,
                         int accumulate, hipStream_t s, int var) {
   (void)var;  // the single-image path uses the default tile
   SweepArgs a{};
@@ -738,23 +741,24 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
   a.recs = it.ctab;
   a.ctab = it.ctab;
   a.labels = labels;
-  a.first = first;
+  a.iter = iter;
   a.done = it.done;
   a.part = it.part;
   a.acc = it.acc;
+  a.accf = it.accf;
   return accumulate ? dispatch<true>(g, img, a, s) : dispatch<false>(g, img, a, s);
 }
 
 hipError_t launch_sweep_batch(int dtype, int nd, int C, int var, const BImg* imgs,
                               const int32_t* tile_img, int tile0, int ntiles,
-                              const int32_t* bin_start, const int32_t* items, const float* recs, int first,
+                              const int32_t* bin_start, const int32_t* items, const float* recs, int iter,
                               unsigned grid, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   grid = (grid + 7) / 8 * 8;
   switch (dtype) {
-    case kU8: return batch_nd<uint8_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    case kU16: return batch_nd<uint16_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
-    default: return batch_nd<float>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, first, grid, s);
+    case kU8: return batch_nd<uint8_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    case kU16: return batch_nd<uint16_t>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
+    default: return batch_nd<float>(nd, C, var, imgs, tile_img, tile0, ntiles, bin_start, items, recs, iter, grid, s);
   }
 }
 

@@ -52,15 +52,16 @@ class Request:
 def footprint(req: Request) -> int:
     """HBM bytes a request holds while admitted: its image, labels, centres
     and counts, and its share of the batch tables (centre records, bins,
-    accumulators and tile slots, about 200 bytes per cluster in 3D)."""
+    accumulators and tile slots, about 600 bytes per cluster in 3D grey)."""
     nd = req.image.dim() - 1
     C = int(req.image.shape[-1])
     dims = tuple(int(d) for d in reversed(req.image.shape[:-1]))
     K = sslic.num_clusters(dims, req.S)
     N = req.voxels
     img = N * C * _BYTES[req.image.dtype]
+    F = 1 + nd + C
     per_cluster = (C + nd) * 8 + 8 + 2 * 4 * ((C + 3 * nd + 4) // 4 * 4) + \
-        (1 + nd + C) * 8 * (1 + (1 << nd)) + 12
+        F * 8 + (F + 1) * 8 * (1 << nd) + 13
     return img + 4 * N + K * per_cluster + 4096
 
 
