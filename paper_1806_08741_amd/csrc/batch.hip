@@ -70,6 +70,7 @@ BImg make_bimg(const Geo& g, int var, const sslic_image_desc& d) {
   b.a.labels = d.labels;
   b.a.ntiles = tiles_of(g, var, b.a.nt);
   b.a.slots = sweep_slots(g, var);
+  b.a.table = sweep_table_suits(g, var);
   sweep_tile_shape(g.nd, b.tdim, var);
   for (int i = g.nd; i < kMaxDim; ++i) b.tdim[i] = 1;
   return b;

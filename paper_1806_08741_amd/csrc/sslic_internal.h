@@ -106,7 +106,13 @@ struct SweepArgs {
   int ntiles;
   int nt[kMaxDim];
   int slots;  // 1: per-cluster tile slots; 0: tiles narrower than a window, atomics only
+  int table;  // 1: tiles list their meeting centres first (see sweep_table_suits)
 };
+// largest cluster count for which a candidate key can carry (k << 6 | lane)
+constexpr int64_t kTableMaxK = (int64_t)1 << 25;
+// 1 when the sweep with tile variant `var` should list each tile's meeting
+// centres first (few enough per tile, cluster indices small enough)
+int sweep_table_suits(const Geo& g, int var);
 // assignment of every voxel (labels) at iteration `iter` (0: voxels outside
 // every window take their grid cell's label, else they keep theirs); with
 // `accumulate`, also the per-cluster sums into it.part (tile slots tagged

@@ -114,8 +114,10 @@ struct TilePack {
   static constexpr int kFields = 1 + ND + (kPackCh ? CC : 0);
   int word[1 + ND + 4];
   int shift[1 + ND + 4];
+  int width[1 + ND + 4];
   int nw;
-  constexpr TilePack() : word(), shift(), nw(0) {
+  int maxw;  // widest field (bits)
+  constexpr TilePack() : word(), shift(), width(), nw(0), maxw(0) {
     uint64_t vox = 1;
     for (int i = 0; i < ND; ++i) vox *= (uint64_t)SH::T[i];
     const uint64_t vmax = std::is_same<T, uint8_t>::value ? 255u : 65535u;
@@ -129,6 +131,8 @@ struct TilePack {
       }
       word[f] = w;
       shift[f] = used;
+      width[f] = b;
+      maxw = b > maxw ? b : maxw;
       used += b;
     }
     nw = w + 1;
@@ -157,15 +161,61 @@ struct RunSum<true> {
   using type = double;
 };
 
+// The packed words of one run (count, tile-relative coordinate sums and, for
+// packed channels, channel sums) assembled on 32-bit halves; each value is
+// below 2^width of its field, and no field is wider than 32 bits.
+template <class PK>
+__device__ __forceinline__ void pack_run(const uint32_t* v, uint64_t* pw) {
+  constexpr PK pk{};
+  static_assert(pk.maxw <= 32, "a run's field must fit 32 bits");
+  uint32_t lo[pk.nw], hi[pk.nw];
+#pragma unroll
+  for (int w = 0; w < pk.nw; ++w) lo[w] = hi[w] = 0;
+#pragma unroll
+  for (int f = 0; f < PK::kFields; ++f) {
+    const int w = pk.word[f], s = pk.shift[f];
+    if (s >= 32) {
+      hi[w] |= v[f] << (s - 32);
+    } else {
+      lo[w] |= v[f] << s;
+      if (s + pk.width[f] > 32) hi[w] |= v[f] >> (32 - s);
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < pk.nw; ++w) pw[w] = (uint64_t)hi[w] << 32 | lo[w];
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // One tile of the sweep: the assignment of its voxels and, with ACC, the
 // per-cluster sums of the tile into the cluster's tile slot or accumulators.
-// s_keys / s_vals: the workgroup's LDS table (SH::kHash entries).
-template <typename T, int ND, int CC, bool ACC, class SH>
-__device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ img,
+//
+// TBL (with ACC): the workgroup first lists every centre whose window meets
+// the tile (from the bins within one bin of the tile), at most 64, in an LDS
+// table: lane l of every wave holds entry l, which is also the cluster's
+// entry in the sum table.  The rows of blocks take their candidates from the
+// lanes, and the best candidate's key carries (k << 6 | lane), so the
+// winner's entry is known without a lookup, and among equal distances the
+// lowest k still wins.  Returns false, before any label is written, when more
+// than 64 centres meet the tile; the caller then runs the hashed form (TBL
+// false), whose sum table is keyed by label and filled from the bins of each
+// row.
+//
+// s_keys: record index per entry (TBL) or hash keys (labels); s_vals: the
+// packed sums per entry; s_tb: per axis, the window bounds relative to the
+// tile, clamped to [-1, T] and biased by 1, low | high << 16 (TBL); s_n: the
+// entry count (TBL).
+template <typename T, int ND, int CC, bool ACC, class SH, bool TBL>
+__device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ img,
                                            const int32_t* __restrict__ bstart,
                                            const int32_t* __restrict__ items,
                                            const float* __restrict__ recs, const SweepArgs& a,
-                                           int iter, int tile, int* s_keys, uint64_t* s_vals) {
+                                           int iter, int tile, int* s_keys, uint64_t* s_vals,
+                                           uint32_t* s_tb, int* s_n) {
+  static_assert(ACC || !TBL, "the table form accumulates");
   using SS = SH;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   constexpr int RN = CM + 3 * ND + 1;  // record words read
@@ -185,12 +235,6 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
   const int tid = threadIdx.x, lane = tid % 64;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
 
-  if constexpr (ACC) {
-    for (int i = tid; i < HS; i += kThreads) s_keys[i] = -1;
-    for (int i = tid; i < HS * EW; i += kThreads) s_vals[i] = 0;
-    __syncthreads();
-  }
-
   int to[ND], tc[ND];
   {
     int r = tile;
@@ -209,8 +253,75 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
     }
   }
 
+  if constexpr (ACC) {
+    if constexpr (!TBL) {
+      for (int i = tid; i < HS; i += kThreads) s_keys[i] = -1;
+    } else {
+      if (tid == 0) *s_n = 0;
+    }
+    for (int i = tid; i < HS * EW; i += kThreads) s_vals[i] = 0;
+    __syncthreads();
+  }
+
+  // --- TBL: the centres whose window meets the tile ---------------------------
+  int n = 0;
+  if constexpr (TBL) {
+    int tl[ND], th[ND], b0[ND], b1[ND];
+    int nrows = 1;
+    for (int i = 0; i < ND; ++i) {
+      tl[i] = to[i];
+      th[i] = min(to[i] + SS::T[i], g.n[i]) - 1;
+      b0[i] = max(tl[i] / g.S[i] - 1, 0);
+      b1[i] = min(th[i] / g.S[i] + 1, g.nb[i] - 1);
+      if (i > 0) nrows *= b1[i] - b0[i] + 1;
+    }
+    for (int r = wave; r < nrows; r += kWaves) {  // one row of bins along axis 0 at a time
+      int bl = b0[0] * (int)g.bst[0], rr = r;
+      for (int i = 1; i < ND; ++i) {
+        const int w = b1[i] - b0[i] + 1;
+        bl += (b0[i] + rr % w) * (int)g.bst[i];
+        rr /= w;
+      }
+      const int ja = bstart[bl], jb = bstart[bl + (b1[0] - b0[0]) + 1];
+      for (int j0 = ja; j0 < jb; j0 += 64) {
+        const int j = j0 + lane;
+        bool keep = j < jb;
+        int rk = 0;
+        uint32_t pb[ND];
+        if (keep) {
+          rk = items[j];
+          const int* irec = reinterpret_cast<const int*>(recs + (int64_t)rk * RS);
+#pragma unroll
+          for (int i = 0; i < ND; ++i) {
+            const int lo = irec[rec_lo(C, ND) + i], hi = irec[rec_hi(C, ND) + i];
+            keep = keep && lo <= th[i] && hi >= tl[i];
+            const int rl = lo < to[i] ? -1 : min(lo - to[i], SS::T[i]);
+            const int rh = hi < to[i] ? -1 : min(hi - to[i], SS::T[i]);
+            pb[i] = (uint32_t)(rl + 1) | (uint32_t)(rh + 1) << 16;
+          }
+        }
+        const uint64_t m = __ballot(keep);
+        if (m == 0) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(s_n, (int)__popcll(m));
+        base = __builtin_amdgcn_readlane(base, 0);
+        if (keep) {
+          const int p = base + lanes_below(m);
+          if (p < 64) {
+            s_keys[p] = rk;
+#pragma unroll
+            for (int i = 0; i < ND; ++i) s_tb[i * 64 + p] = pb[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    n = __builtin_amdgcn_readfirstlane(*s_n);
+    if (n > 64) return false;
+  }
+
   // running sum of this lane's current label (coordinates relative to the tile)
-  int cur = -1;
+  int cur = -1, cslot = -1;
   uint32_t rcnt = 0;
   uint32_t rco[ND];
   RT rch[CM];
@@ -219,39 +330,42 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
 
   auto flush = [&]() {
     if (cur < 0 || rcnt == 0) return;
-    uint32_t h = ((uint32_t)cur * 2654435761u) >> 8;
     int slot = -1;
-    for (int p = 0; p < HS; ++p) {
-      h &= HS - 1;
-      int old = s_keys[h];  // a key once written stays: look before inserting
-      if (old == -1) old = atomicCAS(&s_keys[h], -1, cur);
-      if (old == -1 || old == cur) {
-        slot = (int)h;
-        break;
+    if constexpr (TBL) {
+      slot = cslot;
+    } else {
+      uint32_t h = ((uint32_t)cur * 2654435761u) >> 8;
+      for (int p = 0; p < HS; ++p) {
+        h &= HS - 1;
+        int old = s_keys[h];  // a key once written stays: look before inserting
+        if (old == -1) old = atomicCAS(&s_keys[h], -1, cur);
+        if (old == -1 || old == cur) {
+          slot = (int)h;
+          break;
+        }
+        ++h;
       }
-      ++h;
     }
     if (slot >= 0) {
-      uint64_t pw[NW];
+      uint32_t v[PK::kFields];
+      v[0] = rcnt;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) pw[w] = 0;
-      pw[pk.word[0]] |= (uint64_t)rcnt << pk.shift[0];
-#pragma unroll
-      for (int i = 0; i < ND; ++i) pw[pk.word[1 + i]] |= (uint64_t)rco[i] << pk.shift[1 + i];
+      for (int i = 0; i < ND; ++i) v[1 + i] = rco[i];
       unsigned long long* vv = reinterpret_cast<unsigned long long*>(s_vals + slot * EW);
       if constexpr (PK::kPackCh) {
 #pragma unroll
-        for (int c = 0; c < CM; ++c)
-          pw[pk.word[1 + ND + c]] |= (uint64_t)rch[c] << pk.shift[1 + ND + c];
+        for (int c = 0; c < CM; ++c) v[1 + ND + c] = (uint32_t)rch[c];
       } else {
         for (int c = 0; c < C; ++c) {
           if constexpr (FLT) atomicAdd(reinterpret_cast<double*>(vv + NW + c), (double)rch[c]);
           else atomicAdd(vv + NW + c, (unsigned long long)rch[c]);
         }
       }
+      uint64_t pw[NW];
+      pack_run<PK>(v, pw);
 #pragma unroll
       for (int w = 0; w < NW; ++w) atomicAdd(vv + w, (unsigned long long)pw[w]);
-    } else {  // table full: global accumulators (coordinates made absolute)
+    } else {  // no table entry: global accumulators (coordinates made absolute)
       a.accf[cur] = 1;
       unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)cur * F);
       atomicAdd(gg, (unsigned long long)rcnt);
@@ -288,13 +402,13 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
     return cnt;
   };
 
-  // keeps the smaller (D, k) pair: the lowest cluster index among equal
-  // distances; best starts at FLT_MAX, so +inf (outside the window) never wins
   // The best candidate so far is one 64-bit key: the bits of D (never
-  // negative, so they order as the values do) above the cluster index, so the
-  // smaller key is the smaller D and, among equal D, the lower index.
-  auto pick = [&](float D, int k, uint64_t& bkey) {
-    const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | (uint32_t)k;
+  // negative, so they order as the values do) above the candidate's id, so
+  // the smaller key is the smaller D and, among equal D, the lower id.  The
+  // id is the cluster index, or (index << 6 | holding lane) when TBL rows
+  // find candidates in the table (same order: indices are distinct).
+  auto pick = [&](float D, uint32_t id, uint64_t& bkey) {
+    const uint64_t key = ((uint64_t)__float_as_uint(D) << 32) | id;
     bkey = key < bkey ? key : bkey;
   };
 
@@ -303,7 +417,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
   // whole block (mask mf) need no window test; for the others (mask mc) the
   // closed window is tested on every axis as one unsigned range compare.
   auto scan = [&](uint64_t mf, uint64_t mc, int jo, const int* x, const float* xs,
-                  const float* I, uint64_t& bkey) {
+                  const float* I, bool tagl, uint64_t& bkey) {
     constexpr int RF = CM + ND + 1;  // mu, c', k
     while (mf) {
       const int l = (int)__builtin_ctzll(mf);
@@ -323,9 +437,9 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         const float t = I[c] - R[c];
         D = fmaf(t, t, D);
       }
-      const int k = CC > 0 ? __float_as_int(R[rec_k(CC, ND)])
-                           : reinterpret_cast<const int*>(rec)[rec_k(C, ND)];
-      pick(D, k, bkey);
+      const uint32_t k = CC > 0 ? __float_as_uint(R[rec_k(CC, ND)])
+                                : reinterpret_cast<const uint32_t*>(rec)[rec_k(C, ND)];
+      pick(D, tagl ? k << 6 | (uint32_t)l : k, bkey);
     }
     while (mc) {
       const int l = (int)__builtin_ctzll(mc);
@@ -353,7 +467,8 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         ok &= (uint32_t)(x[i] - lo) <= (uint32_t)(hi - lo);
       }
       D = ok ? D : __builtin_inff();
-      pick(D, Ri[rec_k(C, ND)], bkey);
+      const uint32_t k = (uint32_t)Ri[rec_k(C, ND)];
+      pick(D, tagl ? k << 6 | (uint32_t)l : k, bkey);
     }
   };
 
@@ -393,27 +508,42 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
     }
     if (!rin) continue;
-    // the records of the bins within one bin of the row, one per lane
-    int rb0[ND], rb1[ND];
-    for (int i = 0; i < ND; ++i) {
-      rb0[i] = max(rlo[i] / g.S[i] - 1, 0);
-      rb1[i] = min(rhi[i] / g.S[i] + 1, g.nb[i] - 1);
-    }
-    int rjl = 0;
-    const int nrec = gather(rb0, rb1, rjl);
-    const bool rowfit = nrec <= 64;
-    const bool held = rowfit && lane < nrec;
+    // the row's candidates, one per lane: the lane's record index, window
+    // bounds (tile-relative for TBL) and, for TBL, its table entry
+    bool rowfit, held;
+    int hrk, hslot = 0;
     int hlo[ND], hhi[ND];
-    const int rk = items[held ? rjl : 0];  // the record of the cluster at that bin position
-    const int hjo = rk * RS * 4;
-    {
-      const int* irec = reinterpret_cast<const int*>(recs + (int64_t)rk * RS);
+    if constexpr (TBL) {  // lane l holds entry l
+      rowfit = true;
+      held = lane < n;
+      hslot = held ? lane : 0;
+      hrk = held ? s_keys[hslot] : 0;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const uint32_t pbv = s_tb[i * 64 + hslot];
+        hlo[i] = (int)(pbv & 0xffffu) - 1;
+        hhi[i] = (int)(pbv >> 16) - 1;
+      }
+    } else {
+      // the records of the bins within one bin of the row
+      int rb0[ND], rb1[ND];
+      for (int i = 0; i < ND; ++i) {
+        rb0[i] = max(rlo[i] / g.S[i] - 1, 0);
+        rb1[i] = min(rhi[i] / g.S[i] + 1, g.nb[i] - 1);
+      }
+      int rjl = 0;
+      const int nrec = gather(rb0, rb1, rjl);
+      rowfit = nrec <= 64;
+      held = rowfit && lane < nrec;
+      hrk = items[held ? rjl : 0];  // the record of the cluster at that bin position
+      const int* irec = reinterpret_cast<const int*>(recs + (int64_t)hrk * RS);
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
         hlo[i] = irec[rec_lo(C, ND) + i];
         hhi[i] = irec[rec_hi(C, ND) + i];
       }
     }
+    const int hjo = hrk * RS * 4;
 
     // This lane's voxel in block 0 of the row; block bx is B_0 * bx voxels
     // further along axis 0.  Lanes outside the image read (and never write)
@@ -456,8 +586,17 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       uint64_t bkey = kNone;
       if (rowfit) {
         uint64_t mf, mc;
-        test(held, hlo, hhi, blo, bhi, mf, mc);
-        scan(mf, mc, hjo, x, xs, I, bkey);
+        if constexpr (TBL) {
+          int qlo[ND], qhi[ND];
+          for (int i = 0; i < ND; ++i) {
+            qlo[i] = blo[i] - to[i];
+            qhi[i] = bhi[i] - to[i];
+          }
+          test(held, hlo, hhi, qlo, qhi, mf, mc);
+        } else {
+          test(held, hlo, hhi, blo, bhi, mf, mc);
+        }
+        scan(mf, mc, hjo, x, xs, I, TBL, bkey);
       } else {
         int b0[ND], b1[ND];
         for (int i = 0; i < ND; ++i) {
@@ -477,7 +616,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
           }
           uint64_t mf, mc;
           test(bheld, lo, hi, blo, bhi, mf, mc);
-          scan(mf, mc, bk0 * RS * 4, x, xs, I, bkey);
+          scan(mf, mc, bk0 * RS * 4, x, xs, I, false, bkey);
         } else {
           // more centres than lanes (a crowded neighbourhood): each lane walks them
           int rc[ND];
@@ -503,7 +642,7 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
                 const float t = I[c] - rec[c];
                 D = fmaf(t, t, D);
               }
-              pick(D, irec2[rec_k(C, ND)], bkey);
+              pick(D, (uint32_t)irec2[rec_k(C, ND)], bkey);
             }
             int i = 1;
             while (i < ND) {
@@ -516,13 +655,24 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
         }
       }
       int bk = bkey == kNone ? -1 : (int)(uint32_t)bkey;
+      int bslot = -1;
+      if constexpr (TBL) {
+        if (rowfit) {  // the key holds (k << 6 | lane of the winner's entry)
+          const uint32_t id = (uint32_t)bkey;
+          if (bk >= 0) {
+            bk = (int)(id >> 6);
+            bslot = (int)(id & 63u);  // lane l holds entry l
+          }
+        }
+      }
       if (valid) {
         if (bk < 0) bk = iter == 0 ? grid_label(g, x, ND) : *lp;
         *lp = bk;
         if constexpr (ACC) {
-          if (bk != cur) {
+          if (bk != cur || (TBL && bslot != cslot)) {
             flush();
             cur = bk;
+            cslot = bslot;
             rcnt = 0;
             for (int i = 0; i < ND; ++i) rco[i] = 0;
             for (int c = 0; c < C; ++c) rch[c] = 0;
@@ -538,21 +688,27 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
     }
   }
   if constexpr (!ACC) {
-    return;
+    return true;
   } else {
   flush();
   __syncthreads();
 
   // --- the tile's sums to their cluster slots -------------------------------
   constexpr int NS = 1 << ND;
-  for (int s = tid; s < HS; s += kThreads) {
-    const int k = s_keys[s];
-    if (k < 0) continue;
+  for (int s = tid; s < (TBL ? n : HS); s += kThreads) {
+    int k;
+    if constexpr (TBL) {
+      k = reinterpret_cast<const int*>(recs + (int64_t)s_keys[s] * RS)[rec_k(C, ND)];
+    } else {
+      k = s_keys[s];
+      if (k < 0) continue;
+    }
     const uint64_t* vv = s_vals + s * EW;
-    const uint64_t n = PK::field(vv, 0);
+    const uint64_t nn = PK::field(vv, 0);
+    if (nn == 0) continue;  // a table entry no voxel of the tile took
     uint64_t out[FM];
-    out[0] = n;
-    for (int i = 0; i < ND; ++i) out[1 + i] = PK::field(vv, 1 + i) + n * (uint64_t)to[i];
+    out[0] = nn;
+    for (int i = 0; i < ND; ++i) out[1 + i] = PK::field(vv, 1 + i) + nn * (uint64_t)to[i];
     if constexpr (PK::kPackCh) {
       for (int c = 0; c < CM; ++c) out[1 + ND + c] = PK::field(vv, 1 + ND + c);
     } else {
@@ -588,7 +744,32 @@ __device__ __forceinline__ void sweep_tile(const Geo& g, const T* __restrict__ i
       }
     }
   }
+  return true;
   }
+}
+
+// LDS of one workgroup of the sweep
+template <typename T, int ND, int CC, class SH>
+struct SweepLds {
+  int keys[SH::kHash];
+  uint64_t vals[SH::kHash * entry_words<T, ND, CC, SH>()];
+  uint32_t tb[ND * 64];
+  int n;
+};
+
+// A tile with accumulation: through its table when the sweep allows it and
+// the table holds every meeting centre, else hashed.
+template <typename T, int ND, int CC, class SH>
+__device__ __forceinline__ void sweep_tile_acc(const Geo& g, const T* img, const int32_t* bstart,
+                                               const int32_t* items, const float* recs,
+                                               const SweepArgs& a, int iter, int tile,
+                                               SweepLds<T, ND, CC, SH>& L) {
+  if (a.table && sweep_tile<T, ND, CC, true, SH, true>(g, img, bstart, items, recs, a, iter, tile,
+                                                       L.keys, L.vals, L.tb, &L.n))
+    return;
+  if (a.table) __syncthreads();  // every lane has read the entry count
+  sweep_tile<T, ND, CC, true, SH, false>(g, img, bstart, items, recs, a, iter, tile, L.keys, L.vals,
+                                         L.tb, &L.n);
 }
 
 template <typename T, int ND, int CC, bool ACC>
@@ -597,12 +778,16 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
              const int32_t* __restrict__ items, const float* __restrict__ recs, SweepArgs a) {
   if (*a.done) return;
   using SH = Shape<ND, 0>;
-  __shared__ int s_keys[ACC ? SH::kHash : 1];
-  __shared__ uint64_t s_vals[ACC ? SH::kHash * entry_words<T, ND, CC, SH>() : 1];
   const int per = (int)(gridDim.x / 8);
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (tile >= a.ntiles) return;
-  sweep_tile<T, ND, CC, ACC, SH>(g, img, bstart, items, recs, a, a.iter, tile, s_keys, s_vals);
+  if constexpr (ACC) {
+    __shared__ SweepLds<T, ND, CC, SH> L;
+    sweep_tile_acc<T, ND, CC, SH>(g, img, bstart, items, recs, a, a.iter, tile, L);
+  } else {
+    sweep_tile<T, ND, CC, false, SH, false>(g, img, bstart, items, recs, a, a.iter, tile, nullptr,
+                                            nullptr, nullptr, nullptr);
+  }
 }
 
 // The sweep over the flat tile work-list of a group of images (same pixel
@@ -616,8 +801,7 @@ __global__ void __launch_bounds__(kThreads)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
                    int ntiles, const int32_t* __restrict__ bin_start,
                    const int32_t* __restrict__ items, const float* __restrict__ recs, int iter) {
-  __shared__ int s_keys[SH::kHash];
-  __shared__ uint64_t s_vals[SH::kHash * entry_words<T, ND, CC, SH>()];
+  __shared__ SweepLds<T, ND, CC, SH> L;
   const int xcd = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
   const int chunk = (ntiles + 7) / 8;
   const int end = min((xcd + 1) * chunk, ntiles);
@@ -625,8 +809,8 @@ sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ ti
     const BImg& d = imgs[tile_img[tile0 + t]];
     if (d.flags[0]) continue;
     __syncthreads();  // the previous tile's table is read out
-    sweep_tile<T, ND, CC, true, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
-                                   items, recs, d.a, iter, tile0 + t - d.tile_off, s_keys, s_vals);
+    sweep_tile_acc<T, ND, CC, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
+                                  items, recs, d.a, iter, tile0 + t - d.tile_off, L);
   }
 }
 
@@ -732,6 +916,17 @@ int sweep_slots(const Geo& g, int var) {
   return 1;
 }
 
+// The table form pays off when the centres meeting a tile usually fit one
+// wave: about prod_i (T_i + 2 S_i) / S_i of them on the seed grid.
+int sweep_table_suits(const Geo& g, int var) {
+  if (g.K > kTableMaxK) return 0;
+  int T[kMaxDim];
+  sweep_tile_shape(g.nd, T, var);
+  double e = 1.0;
+  for (int i = 0; i < g.nd; ++i) e *= (double)(T[i] + 2 * g.S[i]) / g.S[i];
+  return e <= 56.0;
+}
+
 hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* labels, int iter,
                         int accumulate, hipStream_t s, int var) {
   (void)var;  // the single-image path uses the default tile
@@ -746,6 +941,7 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
   a.part = it.part;
   a.acc = it.acc;
   a.accf = it.accf;
+  a.table = accumulate && sweep_table_suits(g, 0);
   return accumulate ? dispatch<true>(g, img, a, s) : dispatch<false>(g, img, a, s);
 }
 
