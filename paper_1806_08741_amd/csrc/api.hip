@@ -108,7 +108,6 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
   if (cc) {
     L.cc_parent = put((size_t)g.N * 4);
     L.cc_size = put((size_t)g.N * 4);
-    L.cc_final = put((size_t)g.N);
     L.cc_newlab = put((size_t)g.N * 4);
     L.cc_part = put((size_t)cc_part_ints(g.N) * 4);
     L.cc_roots = put((size_t)g.N * 4);
@@ -159,7 +158,6 @@ CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N) {
   char* b = ctx->ws;
   c.parent = (int32_t*)(b + L.cc_parent);
   c.size = (int32_t*)(b + L.cc_size);
-  c.final_ = (uint8_t*)(b + L.cc_final);
   c.newlab = (int32_t*)(b + L.cc_newlab);
   cc_carve(c, (int32_t*)(b + L.cc_part), N);
   c.roots = (int32_t*)(b + L.cc_roots);

@@ -37,7 +37,7 @@ struct BLayout {
   size_t imgs, cl_img, tile_img, upload_bytes;
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part;
   size_t acc, accf, part, res, flags, nlab;
-  size_t cc_parent, cc_size, cc_final, cc_newlab, cc_part, cc_roots, total;
+  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, total;
 };
 
 std::array<int, 7> key_of(const Geo& g) {
@@ -258,7 +258,6 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
     CCBuf c;
     c.parent = reinterpret_cast<int32_t*>(b + P.L.cc_parent);
     c.size = reinterpret_cast<int32_t*>(b + P.L.cc_size);
-    c.final_ = reinterpret_cast<uint8_t*>(b + P.L.cc_final);
     c.newlab = reinterpret_cast<int32_t*>(b + P.L.cc_newlab);
     cc_carve(c, reinterpret_cast<int32_t*>(b + P.L.cc_part), P.Nmax);
     c.roots = reinterpret_cast<int32_t*>(b + P.L.cc_roots);
@@ -413,7 +412,6 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
     if (P.cc) {
       L.cc_parent = put((size_t)P.Nmax * 4);
       L.cc_size = put((size_t)P.Nmax * 4);
-      L.cc_final = put((size_t)P.Nmax);
       L.cc_newlab = put((size_t)P.Nmax * 4);
       L.cc_part = put((size_t)cc_part_ints(P.Nmax) * 4);
       L.cc_roots = put((size_t)P.Nmax * 4);

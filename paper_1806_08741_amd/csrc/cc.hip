@@ -20,8 +20,10 @@ namespace sslic {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPer = 16;
-constexpr int kBlockVox = kThreads * kPer;
+constexpr int kWaves = kThreads / 64;
+constexpr int kChunk = 1024;                     // voxels one wave ranks: 16 rows of 64
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = kThreads * kScanPer;  // chunk counts one scan block takes
 
 inline int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
@@ -85,11 +87,17 @@ __device__ __forceinline__ void tile_origin(const Geo& g, int tile, int* o) {
   }
 }
 
+// LDS position of local voxel j: one pad word after every 16, so the 64
+// lanes of a wave, each walking its own 16 consecutive voxels, hit distinct
+// banks.
+__device__ __forceinline__ int pd(int j) { return j + (j >> 4); }
+constexpr int kPadVox = kTileVox + kTileVox / 16;
+
 __device__ __forceinline__ int find_local(const int* par, int v) {
-  int p = par[v];
+  int p = par[pd(v)];
   while (p != v) {
     v = p;
-    p = par[v];
+    p = par[pd(v)];
   }
   return v;
 }
@@ -104,16 +112,16 @@ __device__ __forceinline__ void unite_local(int* par, int a, int b) {
       a = b;
       b = t;
     }
-    if (atomicCAS(&par[a], a, b) == a) return;
+    if (atomicCAS(&par[pd(a)], a, b) == a) return;
   }
 }
 
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
-  __shared__ int s_lab[kTileVox];
-  __shared__ int s_par[kTileVox];
-  __shared__ int s_size[kTileVox];
+  __shared__ int s_lab[kPadVox];
+  __shared__ int s_par[kPadVox];
+  __shared__ int s_size[kPadVox];
   int o[ND];
   tile_origin<ND>(g, blockIdx.x, o);
   auto local_coords = [&](int j, int* x) {
@@ -133,14 +141,24 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     }
     return v;
   };
-  for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
-    int x[ND];
-    local_coords(j, x);
-    bool in;
-    const int64_t v = global_index(x, in);
-    s_lab[j] = in ? labels[v] : -1;
-    s_par[j] = j;
-    s_size[j] = 0;
+  {
+    int lab[kSeg];  // all of this thread's loads in flight at once
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      const int j = threadIdx.x + q * kThreads;
+      int x[ND];
+      local_coords(j, x);
+      bool in;
+      const int64_t v = global_index(x, in);
+      lab[q] = in ? labels[v] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      const int j = threadIdx.x + q * kThreads;
+      s_lab[pd(j)] = lab[q];
+      s_par[pd(j)] = j;
+      s_size[pd(j)] = 0;
+    }
   }
   __syncthreads();
   // every thread walks kSeg consecutive voxels of one row along axis 0:
@@ -150,8 +168,8 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     int start = j0;
     for (int q = 1; q < kSeg; ++q) {
       const int j = j0 + q;
-      if (s_lab[j] != s_lab[j - 1]) start = j;
-      s_par[j] = start;
+      if (s_lab[pd(j)] != s_lab[pd(j - 1)]) start = j;
+      s_par[pd(j)] = start;
     }
   }
   __syncthreads();
@@ -160,15 +178,16 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   {
     int x0[ND];
     local_coords(j0, x0);
-    if (x0[0] > 0 && s_lab[j0] >= 0 && s_lab[j0] == s_lab[j0 - 1]) unite_local(s_par, j0 - 1, j0);
+    if (x0[0] > 0 && s_lab[pd(j0)] >= 0 && s_lab[pd(j0)] == s_lab[pd(j0 - 1)])
+      unite_local(s_par, j0 - 1, j0);
     int sh = CCTile<ND>::L[0];
     for (int i = 1; i < ND; ++i) {
       if (x0[i] > 0) {
         const int d = 1 << sh;
         for (int q = 0; q < kSeg; ++q) {
-          const int j = j0 + q, l = s_lab[j];
-          if (l < 0 || s_lab[j - d] != l) continue;
-          if (q > 0 && s_lab[j - 1] == l && s_lab[j - 1 - d] == l) continue;  // same pair of runs
+          const int j = j0 + q, l = s_lab[pd(j)];
+          if (l < 0 || s_lab[pd(j - d)] != l) continue;
+          if (q > 0 && s_lab[pd(j - 1)] == l && s_lab[pd(j - 1 - d)] == l) continue;  // same pair of runs
           unite_local(s_par, j - d, j);
         }
       }
@@ -176,35 +195,35 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < kTileVox; j += kThreads) s_par[j] = find_local(s_par, j);
+  for (int j = threadIdx.x; j < kTileVox; j += kThreads) s_par[pd(j)] = find_local(s_par, j);
   __syncthreads();
   {  // sizes: each thread counts 16 consecutive voxels, one atomic per run
     const int j0 = threadIdx.x * (kTileVox / kThreads);
     int cur = -1, n = 0;
     for (int q = 0; q < kTileVox / kThreads; ++q) {
       const int j = j0 + q;
-      if (s_lab[j] < 0) continue;
-      const int r = s_par[j];
+      if (s_lab[pd(j)] < 0) continue;
+      const int r = s_par[pd(j)];
       if (r != cur) {
-        if (n) atomicAdd(&s_size[cur], n);
+        if (n) atomicAdd(&s_size[pd(cur)], n);
         cur = r;
         n = 0;
       }
       ++n;
     }
-    if (n) atomicAdd(&s_size[cur], n);
+    if (n) atomicAdd(&s_size[pd(cur)], n);
   }
   __syncthreads();
   for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
-    if (s_lab[j] < 0) continue;
+    if (s_lab[pd(j)] < 0) continue;
     int x[ND], xr[ND];
     local_coords(j, x);
     bool in;
     const int64_t v = global_index(x, in);
-    local_coords(s_par[j], xr);
+    local_coords(s_par[pd(j)], xr);
     const int64_t r = global_index(xr, in);
     b.parent[v] = (int32_t)r;
-    b.size[v] = s_size[j];  // non-zero exactly at local roots
+    b.size[v] = s_size[pd(j)];  // non-zero exactly at local roots
   }
 }
 
@@ -239,13 +258,85 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   }
 }
 
-__global__ void cc_flatten_kernel(Geo g, CCBuf b) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const int r = find_root(b.parent, (int)v);
-    const int s = b.size[v];
-    if (s > 0 && r != (int)v) atomicAdd(&b.size[r], s);  // a local root joins its global root
-    if (r == (int)v) b.final_[v] = 0;
+// Global roots, per tile: each local root (local size > 0) finds its root
+// after the face unions and adds its size there; every other voxel of the
+// tile points at a local root of the tile, whose global root it then takes
+// from LDS.
+template <int ND>
+__global__ void __launch_bounds__(kThreads)
+cc_flatten_kernel(Geo g, CCBuf b) {
+  __shared__ int s_root[kTileVox];
+  __shared__ uint32_t s_isr[kTileVox / 32];  // local roots
+  int o[ND];
+  tile_origin<ND>(g, blockIdx.x, o);
+  int64_t base = 0;
+  float inv[ND];
+  for (int i = 0; i < ND; ++i) {
+    base += (int64_t)o[i] * g.st[i];
+    inv[i] = 1.0f / (float)g.st[i];
+  }
+  for (int j = threadIdx.x; j < kTileVox / 32; j += kThreads) s_isr[j] = 0;
+  __syncthreads();
+  auto voxel = [&](int j, int64_t& v) {
+    int sh = 0;
+    bool in = true;
+    v = 0;
+    for (int i = 0; i < ND; ++i) {
+      const int gx = o[i] + ((j >> sh) & ((1 << CCTile<ND>::L[i]) - 1));
+      sh += CCTile<ND>::L[i];
+      in = in && gx < g.n[i];
+      v += (int64_t)gx * g.st[i];
+    }
+    return in;
+  };
+  int sz[kSeg], par[kSeg];  // all of this thread's loads in flight at once
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    int64_t v;
+    const bool in = voxel(threadIdx.x + q * kThreads, v);
+    sz[q] = in ? b.size[v] : 0;
+    par[q] = in ? b.parent[v] : -1;
+  }
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    if (sz[q] <= 0) continue;
+    const int j = threadIdx.x + q * kThreads;
+    int64_t v;
+    voxel(j, v);
+    const int r = par[q] == (int)v ? (int)v : find_root(b.parent, (int)v);
+    s_root[j] = r;
+    atomicOr(&s_isr[j >> 5], 1u << (j & 31));
+    if (r != (int)v) atomicAdd(&b.size[r], sz[q]);  // a local root joins its global root
+    par[q] = -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    int64_t v;
+    if (!voxel(j, v)) continue;
+    int r;
+    if (par[q] < 0) {
+      r = s_root[j];  // a local root
+    } else {
+      // the local root's tile-local index from its offset to the tile origin
+      int64_t d = (int64_t)par[q] - base;
+      int lj = 0, sh = 0;
+      int xq[ND];
+      for (int i = ND - 1; i >= 1; --i) {
+        int qi = (int)((float)d * inv[i]);
+        if ((int64_t)qi * g.st[i] > d) --qi;
+        else if ((int64_t)(qi + 1) * g.st[i] <= d) ++qi;
+        xq[i] = qi;
+        d -= (int64_t)qi * g.st[i];
+      }
+      xq[0] = (int)d;
+      for (int i = 0; i < ND; ++i) {
+        lj |= xq[i] << sh;
+        sh += CCTile<ND>::L[i];
+      }
+      r = s_root[lj];
+    }
     b.parent[v] = r;
   }
 }
@@ -294,59 +385,61 @@ __global__ void cc_first_kernel(Geo g, const double* __restrict__ cen,
   }
   if (seed < 0) return;
   int r = b.parent[seed];
-  if (4 * (int64_t)b.size[r] > g.prodS) b.final_[r] = 1;
+  // a component holds one label, so no other cluster marks it
+  const int sz = b.size[r];
+  if (sz >= 0 && 4 * (int64_t)sz > g.prodS) b.size[r] = ~sz;
 }
 
-__device__ __forceinline__ bool large_open_root(const Geo& g, const CCBuf& b, int64_t v) {
-  return !b.final_[v] && 4 * (int64_t)b.size[v] > g.prodS;
+
+// Wave w of block x ranks chunk c = 4x + w: voxels [1024 c, 1024 c + 1024)
+// as 16 coalesced rows of 64, in raster order.
+__device__ __forceinline__ int64_t wave_chunk() {
+  return (int64_t)blockIdx.x * kWaves + threadIdx.x / 64;
 }
 
-// The roots (and, among them, the large open ones) of block `blk`'s 4096
-// voxels, visited as 16 coalesced rows of 256 in raster order; f(v, large,
-// rank_large, rank_root) is called for every root with its ranks inside the
-// block.  Returns the block totals (thread 0).
-template <class Fn>
-__device__ __forceinline__ void block_roots(const Geo& g, const CCBuf& b, int64_t blk, int* sh,
-                                            int& tot_large, int& tot_root, Fn f) {
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  constexpr int W = kThreads / 64;
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  int run_l = 0, run_r = 0;
-  for (int j = 0; j < kPer; ++j) {
-    const int64_t v = blk * kBlockVox + (int64_t)j * kThreads + threadIdx.x;
-    const bool root = v < g.N && b.parent[v] == (int32_t)v;
-    const bool large = root && large_open_root(g, b, v);
-    const uint64_t mr = __ballot(root), ml = __ballot(large);
-    if (lane == 0) {
-      sh[wv] = __popcll(ml);
-      sh[W + wv] = __popcll(mr);
-    }
-    __syncthreads();
-    int off_l = 0, off_r = 0, all_l = 0, all_r = 0;
-    for (int w = 0; w < W; ++w) {
-      if (w < wv) {
-        off_l += sh[w];
-        off_r += sh[W + w];
-      }
-      all_l += sh[w];
-      all_r += sh[W + w];
-    }
-    __syncthreads();
-    if (root) f(v, large, run_l + off_l + __popcll(ml & lt), run_r + off_r + __popcll(mr & lt));
-    run_l += all_l;
-    run_r += all_r;
+constexpr int kRows = kChunk / 64;
+
+// Which of this lane's voxels of chunk c (one per row) are roots, and large
+// open ones; all loads of a kind in flight at once.
+__device__ __forceinline__ void chunk_roots(const Geo& g, const CCBuf& b, int64_t c, bool* root,
+                                            bool* large, bool* fin) {
+  const int lane = threadIdx.x % 64;
+  int par[kRows];
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    const int64_t v = c * kChunk + q * 64 + lane;
+    par[q] = v < g.N ? b.parent[v] : -1;
   }
-  tot_large = run_l;
-  tot_root = run_r;
+  int sz[kRows];
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    const int64_t v = c * kChunk + q * 64 + lane;
+    root[q] = par[q] == (int32_t)v;
+    sz[q] = root[q] ? b.size[v] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    fin[q] = sz[q] < 0;  // marked final by the first pass
+    large[q] = root[q] && !fin[q] && 4 * (int64_t)sz[q] > g.prodS;
+  }
 }
 
-__global__ void __launch_bounds__(kThreads) cc_count_kernel(Geo g, CCBuf b) {
-  __shared__ int sh[2 * (kThreads / 64)];
-  int tl, tr;
-  block_roots(g, b, blockIdx.x, sh, tl, tr, [](int64_t, bool, int, int) {});
-  if (threadIdx.x == 0) {
-    b.part[blockIdx.x] = tl;
-    b.rpart[blockIdx.x] = tr;
+// Roots and large open roots per chunk.
+__global__ void __launch_bounds__(kThreads) cc_count_kernel(Geo g, CCBuf b, int64_t nchunks) {
+  const int lane = threadIdx.x % 64;
+  const int64_t c = wave_chunk();
+  if (c >= nchunks) return;
+  bool root[kRows], large[kRows], fin[kRows];
+  chunk_roots(g, b, c, root, large, fin);
+  int nl = 0, nr = 0;
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    nr += (int)__popcll(__ballot(root[q]));
+    nl += (int)__popcll(__ballot(large[q]));
+  }
+  if (lane == 0) {
+    b.part[c] = nl;
+    b.rpart[c] = nr;
   }
 }
 
@@ -366,23 +459,53 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) 
   return incl - v;
 }
 
-// exclusive scans of both block count arrays; totals to b.total / b.nroots
-__global__ void cc_scan_parts_kernel(CCBuf b, int nparts) {
+// Exclusive scan of both chunk count arrays, in three steps: each block
+// scans kScanBlock counts in place and leaves its total ...
+__global__ void __launch_bounds__(kThreads) cc_scan_local_kernel(CCBuf b, int64_t n) {
   __shared__ int sh[kThreads];
   for (int which = 0; which < 2; ++which) {
-    int32_t* part = which ? b.rpart : b.part;
+    int32_t* a = which ? b.rpart : b.part;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+      v[j] = base + j < n ? a[base + j] : 0;
+      sum += v[j];
+    }
+    int total;
+    int off = block_exclusive_scan(sum, sh, &total);
+    for (int j = 0; j < kScanPer; ++j) {
+      if (base + j < n) a[base + j] = off;
+      off += v[j];
+    }
+    if (threadIdx.x == 0) (which ? b.brpart : b.bpart)[blockIdx.x] = total;
+  }
+}
+
+// ... one block scans the block totals (grand totals to b.total, b.nroots) ...
+__global__ void __launch_bounds__(kThreads) cc_scan_blocks_kernel(CCBuf b, int nblocks) {
+  __shared__ int sh[kThreads];
+  for (int which = 0; which < 2; ++which) {
+    int32_t* p = which ? b.brpart : b.bpart;
     int carry = 0;
-    for (int b0 = 0; b0 < nparts; b0 += kThreads) {
-      int i = b0 + threadIdx.x;
-      int v = i < nparts ? part[i] : 0;
+    for (int b0 = 0; b0 < nblocks; b0 += kThreads) {
+      const int i = b0 + threadIdx.x;
+      const int v = i < nblocks ? p[i] : 0;
       int total;
-      int ex = block_exclusive_scan(v, sh, &total);
-      if (i < nparts) part[i] = ex + carry;
+      const int ex = block_exclusive_scan(v, sh, &total);
+      if (i < nblocks) p[i] = ex + carry;
       carry += total;
-      __syncthreads();
     }
     if (threadIdx.x == 0) *(which ? b.nroots : b.total) = carry;
   }
+}
+
+// ... and every count gets its block's offset.
+__global__ void cc_scan_add_kernel(CCBuf b, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  b.part[i] += b.bpart[i / kScanBlock];
+  b.rpart[i] += b.brpart[i / kScanBlock];
 }
 
 // Label of every root: final roots keep their label, large open roots get
@@ -390,54 +513,80 @@ __global__ void cc_scan_parts_kernel(CCBuf b, int nparts) {
 // -(root of their predecessor) - 1 to be resolved.  The roots are listed in
 // raster order as they go.
 __global__ void __launch_bounds__(kThreads)
-cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
-  __shared__ int sh[2 * (kThreads / 64)];
-  const int base_l = b.part[blockIdx.x], base_r = b.rpart[blockIdx.x];
-  int tl, tr;
-  block_roots(g, b, blockIdx.x, sh, tl, tr, [&](int64_t v, bool large, int rl, int rr) {
-    int lab;
-    if (b.final_[v]) {
-      lab = labels[v];
-    } else if (large) {
-      lab = (int)(g.K + base_l + rl);
-    } else if (v == 0) {
-      lab = labels[0];
-    } else {
-      int64_t pred = -1, r = v;
-      for (int i = 0; i < g.nd && pred < 0; ++i) {
-        int xi = (int)(r % g.n[i]);
-        r /= g.n[i];
-        if (xi > 0) pred = v - g.st[i];
+cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b, int64_t nchunks) {
+  const int lane = threadIdx.x % 64;
+  const int64_t c = wave_chunk();
+  if (c >= nchunks) return;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int rl = b.part[c], rr = b.rpart[c];
+  bool rootq[kRows], largeq[kRows], finq[kRows];
+  chunk_roots(g, b, c, rootq, largeq, finq);
+#pragma unroll
+  for (int q = 0; q < kRows; ++q) {
+    const int64_t v = c * kChunk + q * 64 + lane;
+    const bool root = rootq[q], large = largeq[q];
+    const uint64_t mr = __ballot(root), ml = __ballot(large);
+    if (root) {
+      int lab;
+      if (finq[q]) {
+        lab = labels[v];
+      } else if (large) {
+        lab = (int)(g.K + rl + __popcll(ml & lt));
+      } else if (v == 0) {
+        lab = labels[0];
+      } else {
+        // the face neighbour before v: along the first axis where v is not
+        // at the low border (indices fit 32 bits)
+        uint32_t r = (uint32_t)v;
+        int64_t pred = -1;
+        for (int i = 0; i < g.nd && pred < 0; ++i) {
+          const uint32_t q2 = r / (uint32_t)g.n[i];
+          if (r - q2 * (uint32_t)g.n[i] > 0) pred = v - g.st[i];
+          r = q2;
+        }
+        lab = -(b.parent[pred]) - 1;
       }
-      lab = -(b.parent[pred]) - 1;
+      b.newlab[v] = lab;
+      b.roots[rr + __popcll(mr & lt)] = (int32_t)v;
     }
-    b.newlab[v] = lab;
-    b.roots[base_r + rr] = (int32_t)v;
-  });
-}
-
-// Small roots follow their links to a resolved label (links go to strictly
-// smaller roots, so every chain ends).
-__global__ void cc_resolve_kernel(Geo g, CCBuf b) {
-  const int n = *b.nroots;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int v = b.roots[i];
-    int lab = b.newlab[v];
-    if (lab >= 0) continue;
-    int t = -lab - 1;
-    int lt = b.newlab[t];
-    while (lt < 0) {
-      t = -lt - 1;
-      lt = b.newlab[t];
-    }
-    b.newlab[v] = lt;
+    rl += (int)__popcll(ml);
+    rr += (int)__popcll(mr);
   }
 }
 
-__global__ void cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, int32_t* n_labels) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N;
-       v += (int64_t)gridDim.x * blockDim.x)
-    labels[v] = b.newlab[b.parent[v]];
+// Small roots take the label their link leads to (most links end at once:
+// the neighbour before a small root usually lies in a large or final
+// component).  Lanes take consecutive roots, and each thread follows four
+// chains at a time.  Every root's entry is written once, by its own thread,
+// from link to label, so any entry read on the way is valid.
+__global__ void __launch_bounds__(kThreads) cc_resolve_kernel(CCBuf b) {
+  constexpr int U = 4;
+  const int n = *b.nroots;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+    int v[U], lab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i0 + u * stride < n ? b.roots[i0 + u * stride] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) lab[u] = v[u] >= 0 ? b.newlab[v[u]] : 0;
+    int w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = lab[u] < 0 ? b.newlab[-lab[u] - 1] : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (lab[u] >= 0) continue;
+      int lu = w[u];
+      while (lu < 0) lu = b.newlab[-lu - 1];
+      b.newlab[v[u]] = lu;
+    }
+  }
+}
+
+// Every voxel takes the label of its component's root.
+__global__ void __launch_bounds__(kThreads)
+cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, int32_t* n_labels) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v < g.N) labels[v] = b.newlab[b.parent[v]];
   if (n_labels && blockIdx.x == 0 && threadIdx.x == 0) *n_labels = (int32_t)(g.K + *b.total);
 }
 
@@ -445,8 +594,9 @@ __global__ void cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, 
 
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels, const CCBuf& b,
                                int32_t* n_labels_dev, hipStream_t s) {
-  int nv = (int)std::min<int64_t>(blocks_for(g.N), 1 << 18);
-  int nparts = (int)((g.N + kBlockVox - 1) / kBlockVox);
+  const int64_t nchunks = (g.N + kChunk - 1) / kChunk;
+  const int nwg = (int)((nchunks + kWaves - 1) / kWaves);
+  const int nsb = (int)((nchunks + kScanBlock - 1) / kScanBlock);
   int ntiles = 1;
   for (int i = 0; i < g.nd; ++i) {
     const int L = g.nd == 2 ? CCTile<2>::L[i] : g.nd == 3 ? CCTile<3>::L[i] : CCTile<4>::L[i];
@@ -456,23 +606,27 @@ hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
     case 2:
       cc_local_kernel<2><<<ntiles, kThreads, 0, s>>>(g, labels, b);
       cc_faces_kernel<2><<<ntiles, kThreads, 0, s>>>(g, labels, b);
+      cc_flatten_kernel<2><<<ntiles, kThreads, 0, s>>>(g, b);
       break;
     case 3:
       cc_local_kernel<3><<<ntiles, kThreads, 0, s>>>(g, labels, b);
       cc_faces_kernel<3><<<ntiles, kThreads, 0, s>>>(g, labels, b);
+      cc_flatten_kernel<3><<<ntiles, kThreads, 0, s>>>(g, b);
       break;
     default:
       cc_local_kernel<4><<<ntiles, kThreads, 0, s>>>(g, labels, b);
       cc_faces_kernel<4><<<ntiles, kThreads, 0, s>>>(g, labels, b);
+      cc_flatten_kernel<4><<<ntiles, kThreads, 0, s>>>(g, b);
       break;
   }
-  cc_flatten_kernel<<<nv, kThreads, 0, s>>>(g, b);
   cc_first_kernel<<<blocks_for(g.K), kThreads, 0, s>>>(g, cen, labels, b);
-  cc_count_kernel<<<nparts, kThreads, 0, s>>>(g, b);
-  cc_scan_parts_kernel<<<1, kThreads, 0, s>>>(b, nparts);
-  cc_root_labels_kernel<<<nparts, kThreads, 0, s>>>(g, labels, b);
-  cc_resolve_kernel<<<(int)std::min<int64_t>(blocks_for(g.N), 4096), kThreads, 0, s>>>(g, b);
-  cc_relabel_kernel<<<nv, kThreads, 0, s>>>(g, labels, b, n_labels_dev);
+  cc_count_kernel<<<nwg, kThreads, 0, s>>>(g, b, nchunks);
+  cc_scan_local_kernel<<<nsb, kThreads, 0, s>>>(b, nchunks);
+  cc_scan_blocks_kernel<<<1, kThreads, 0, s>>>(b, nsb);
+  cc_scan_add_kernel<<<blocks_for(nchunks), kThreads, 0, s>>>(b, nchunks);
+  cc_root_labels_kernel<<<nwg, kThreads, 0, s>>>(g, labels, b, nchunks);
+  cc_resolve_kernel<<<(int)std::min<int64_t>(blocks_for(g.N), 1 << 16), kThreads, 0, s>>>(b);
+  cc_relabel_kernel<<<blocks_for(g.N), kThreads, 0, s>>>(g, labels, b, n_labels_dev);
   return hipGetLastError();
 }
 

@@ -183,21 +183,28 @@ hipError_t launch_residual_finish(const Iter& it, int t, double tol, double* res
 // connectivity scratch
 struct CCBuf {
   int32_t* parent;    // [N]
-  int32_t* size;      // [N]
-  uint8_t* final_;    // [N]
+  int32_t* size;      // [N] component sizes at roots (~size: marked final)
   int32_t* newlab;    // [N] label of each component root
-  int32_t* part;      // [ceil(N / 4096) + 1] large open roots per block, then offsets
-  int32_t* rpart;     // [ceil(N / 4096) + 1] roots per block, then offsets
+  int32_t* part;      // [ceil(N / 1024) + 1] large open roots per chunk, then offsets
+  int32_t* rpart;     // [ceil(N / 1024) + 1] roots per chunk, then offsets
+  int32_t* bpart;     // [ceil(chunks / 4096) + 1] scan partials of part
+  int32_t* brpart;    // [ceil(chunks / 4096) + 1] scan partials of rpart
   int32_t* roots;     // [N] the roots in raster order
   int32_t* total;     // [1] number of new labels
   int32_t* nroots;    // [1] number of roots
 };
-// ints the block counts of CCBuf take (part, rpart, nroots), and their carving
-inline int64_t cc_part_ints(int64_t N) { return 2 * (N / 4096 + 2) + 2; }
+// ints the chunk counts of CCBuf take (part, rpart, bpart, brpart, nroots),
+// and their carving
+inline int64_t cc_chunks(int64_t N) { return N / 1024 + 2; }
+inline int64_t cc_scan_blocks(int64_t N) { return cc_chunks(N) / 4096 + 2; }
+inline int64_t cc_part_ints(int64_t N) { return 2 * cc_chunks(N) + 2 * cc_scan_blocks(N) + 2; }
 inline void cc_carve(CCBuf& c, int32_t* region, int64_t N) {
+  const int64_t nc = cc_chunks(N), nb = cc_scan_blocks(N);
   c.part = region;
-  c.rpart = region + (N / 4096 + 2);
-  c.nroots = region + 2 * (N / 4096 + 2);
+  c.rpart = region + nc;
+  c.bpart = region + 2 * nc;
+  c.brpart = region + 2 * nc + nb;
+  c.nroots = region + 2 * nc + 2 * nb;
 }
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
                                const CCBuf& b, int32_t* n_labels_dev, hipStream_t s);
