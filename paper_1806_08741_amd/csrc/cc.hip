@@ -119,9 +119,9 @@ __device__ __forceinline__ void unite_local(int* par, int a, int b) {
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
-  __shared__ int s_lab[kPadVox];
+  __shared__ int s_lab[kPadVox];  // labels, then (once unions are done) local sizes
   __shared__ int s_par[kPadVox];
-  __shared__ int s_size[kPadVox];
+  int* s_size = s_lab;
   int o[ND];
   tile_origin<ND>(g, blockIdx.x, o);
   auto local_coords = [&](int j, int* x) {
@@ -157,7 +157,6 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
       const int j = threadIdx.x + q * kThreads;
       s_lab[pd(j)] = lab[q];
       s_par[pd(j)] = j;
-      s_size[pd(j)] = 0;
     }
   }
   __syncthreads();
@@ -197,12 +196,19 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   __syncthreads();
   for (int j = threadIdx.x; j < kTileVox; j += kThreads) s_par[pd(j)] = find_local(s_par, j);
   __syncthreads();
+  // labels are no longer needed: voxels outside the image get parent -1 and
+  // the label words become the size counters
+  for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
+    if (s_lab[pd(j)] < 0) s_par[pd(j)] = -1;
+    s_size[pd(j)] = 0;
+  }
+  __syncthreads();
   {  // sizes: each thread counts 16 consecutive voxels, one atomic per run
     const int j0 = threadIdx.x * (kTileVox / kThreads);
     int cur = -1, n = 0;
     for (int q = 0; q < kTileVox / kThreads; ++q) {
       const int j = j0 + q;
-      if (s_lab[pd(j)] < 0) continue;
+      if (s_par[pd(j)] < 0) continue;
       const int r = s_par[pd(j)];
       if (r != cur) {
         if (n) atomicAdd(&s_size[pd(cur)], n);
@@ -215,7 +221,7 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   }
   __syncthreads();
   for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
-    if (s_lab[pd(j)] < 0) continue;
+    if (s_par[pd(j)] < 0) continue;
     int x[ND], xr[ND];
     local_coords(j, x);
     bool in;
