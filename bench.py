@@ -8,9 +8,12 @@ slide-like 2D RGB uint8 16384x16384 image (S=16, m=10, 10 iterations, no
 connectivity).  Prints one JSON line:
 
   value          Mvoxel*iter/s = voxels * iterations * steps / timed seconds
-  roofline       the dominant kernel's algorithmic bytes per launch / its mean
+  roofline       the dominant kernel (the sweep) is bound by vector ALU
+                 issue: its algorithmic FP32 flops per launch / its mean
                  launch time (HIP events on the launch stream, timed region),
-                 against the 8 TB/s HBM peak; ``traffic`` comes from committed
+                 against the FP32 vector peak without packed FP32; the same
+                 launch time against the 8 TB/s HBM peak for its algorithmic
+                 bytes is reported beside it; ``traffic`` comes from committed
                  rocprofv3 FETCH_SIZE/WRITE_SIZE counters when they were taken
                  on the current kernel source, else null
   cpu_baseline   the FP64 oracle (single thread) on a crop of the same image
@@ -29,6 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak with packed FP32 disabled (as this build compiles every
+# kernel): 256 CUs x 64 lanes x 2 flops per FMA x 2.4 GHz = 78.6 TFLOP/s (the
+# published 157.3 counts packed FP32 dual issue)
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 BYTES = {"u8": 1, "u16": 2, "f32": 4}
 
 
@@ -294,6 +301,15 @@ def main():
     bytes_launch = N * per_vox
     achieved = bytes_launch / (prof[dom]["ms_mean"] * 1e-3) / 1e9
     traffic = load_traffic(dom, w.name)
+    # algorithmic FP32 work: every window covering a voxel costs one distance,
+    # 3 flops per term (difference, multiply-add) over nd + C terms, with the
+    # compare in place of the first term's add; windows cover K prod(2 S_i)
+    # voxels in all (centres off the integer grid, no clipping)
+    nd = len(w.dims)
+    cover = K * float(np.prod([2 * s for s in w.S])) / N
+    flops_vox = cover * 3 * (nd + w.channels)
+    flops_launch = N * flops_vox
+    tflops = flops_launch / (prof[dom]["ms_mean"] * 1e-3) / 1e12
     rec = {
         "metric": "SLIC Mvoxel*iter/s (whole sslic_run per step; inputs resident in HBM)",
         "value": round(value, 1),
@@ -311,10 +327,15 @@ def main():
                    "image_dtype": dt_name, "S": list(w.S), "m": w.m,
                    "iterations": w.iterations, "connectivity": w.connectivity, "K": K,
                    "recipe": w.recipe},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": bytes_launch},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3),
+                     "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                     "frac": round(tflops / ALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic,
+                     "algorithmic_flops_per_launch": round(flops_launch),
+                     "flops_per_voxel": round(flops_vox, 2),
+                     "hbm_achieved": round(achieved, 1), "hbm_peak": HBM_PEAK_GBS,
+                     "hbm_unit": "GB/s", "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": bytes_launch},
         "kernels_ms": {k: round(v["ms_mean"], 4) for k, v in prof.items()},
     }
     crop = args.cpu_crop if args.cpu_crop >= 0 else (4096 if len(w.dims) == 2 else 224)
