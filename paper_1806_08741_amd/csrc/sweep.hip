@@ -5,29 +5,33 @@
 //
 // Work decomposition
 //   * A workgroup owns a tile (2D 64x64, 3D 32x32x32, 4D 16x16x8x8); each of
-//     its four waves sweeps a run of blocks of 64 voxels (8x8, 4x4x4,
-//     4x4x2x2) along axis 0.
-//   * For a block, lane i loads the bounds of the i-th centre record in the
-//     bins within one bin of the block (records are stored in bin order, so a
-//     row of bins is one contiguous range), tests whether its window meets the
-//     block and on which axes it cuts it, and a ballot keeps the meeting ones.
-//     The wave then takes them one by one (s_ff1 on the ballot) and reads each
-//     record with scalar loads, so the means and scaled coordinates are
-//     scalar operands of the distance arithmetic:
+//     its four waves sweeps rows of blocks of 64 voxels (8x8, 4x4x4,
+//     4x4x2x2) along axis 0, one voxel per lane.
+//   * Candidates, one centre record per lane: either the tile's table (the
+//     centres whose window meets the tile, when at most 64; lane l holds
+//     entry l), or per row of blocks the records of the bins within one bin
+//     of the row (a row of bins is one contiguous range of the bin-ordered
+//     item list).  For a block, each lane tests whether its centre's window
+//     meets the block and whether it covers it, and ballots keep the meeting
+//     ones.  The wave then takes them one by one (s_ff1 on the ballot) and
+//     reads each record with scalar loads, so the means and scaled
+//     coordinates are scalar operands of the distance:
 //       D^2 = sum_i (x_i m / S_i - c'_i)^2 + sum_c (I_c - mu_c)^2   (FP32).
-//     Centres are visited in raster order of their bins; while cluster indices
-//     keep increasing a strict "<" keeps the lowest index among equal
-//     distances, otherwise the index is compared as well.
+//     The best is one 64-bit key (bits of D, then the cluster index, or the
+//     index and the holding lane), so among equal distances the lowest
+//     index wins.
 //   * Each lane keeps a running sum for its current label across the blocks
 //     of its run (labels are spatially coherent); when the label changes the
-//     run is added to a per-tile LDS table keyed by label.
+//     run is added to the tile's LDS sum table: at the winner's table entry,
+//     or at the entry a hash of the label finds.
 //   * At the end the table goes to global memory without atomics: each
 //     cluster has 2^n slots, one per tile its window can meet (a window spans
 //     at most two tiles per axis when the tile is at least 2S+1 wide), chosen
-//     by the tile's offset from the tile that holds the window's low corner.
-//     Sums for labels outside the window's tiles (voxels that no window
-//     reached keep an older label) and every sum when the tiles are too small
-//     for slots go through 64-bit atomics into the plain accumulators instead.
+//     by the tile's offset from the tile that holds the window's low corner,
+//     and tagged with the iteration.  Sums for labels outside the window's
+//     tiles (voxels that no window reached keep an older label) and every
+//     sum when the tiles are too small for slots go through 64-bit atomics
+//     into the plain accumulators instead, which are flagged per cluster.
 #include "sslic_internal.h"
 
 namespace sslic {

@@ -42,12 +42,26 @@ KERNELS = {
 }
 
 
+def code_lines(text: str) -> str:
+    """The code of a C/HIP source: line comments, trailing blanks and empty
+    lines dropped (a comment edit does not change what the counters saw)."""
+    out = []
+    for line in text.splitlines():
+        i = line.find("//")
+        while i >= 0 and line.count('"', 0, i) % 2 == 1:  # "//" inside a string
+            i = line.find("//", i + 2)
+        code = (line if i < 0 else line[:i]).rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def kernel_source_hash(kernel: str) -> str:
-    """Hash of the sources a kernel class is built from (staleness of counters)."""
+    """Hash of the code a kernel class is built from (staleness of counters)."""
     h = hashlib.sha256()
     for f in KERNELS[kernel][1]:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", f), encoding="utf-8") as fh:
+            h.update(code_lines(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
