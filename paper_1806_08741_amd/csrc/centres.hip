@@ -121,6 +121,98 @@ __global__ void seed_kernel(Geo g, const T* __restrict__ img, double* __restrict
   seed_one<T>(g, img, cen, k);
 }
 
+// The same search with ND and C fixed at compile time: the values the
+// 3^ND gradients read (the clamped voxels s + d with every |d_i| <= 1 but
+// at most one |d_i| = 2) are loaded first, all at once, then the gradients
+// are formed from registers in the order above (c outer, axis inner).
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <typename T, int ND, int CC>
+__global__ void __launch_bounds__(kThreads)
+seed_fixed_kernel(Geo g, const T* __restrict__ img, double* __restrict__ cen) {
+  using G = typename std::conditional<std::is_same<T, float>::value, double, int64_t>::type;
+  constexpr int P5 = ipow(5, ND), N3 = ipow(3, ND);
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= g.K) return;
+  int s[ND];
+  {
+    int64_t r = k;
+    for (int i = 0; i < ND; ++i) {
+      const int64_t j = r % g.Ka[i];
+      r /= g.Ka[i];
+      s[i] = (int)(((2 * j + 1) * (int64_t)g.n[i]) / (2 * (int64_t)g.Ka[i]));
+    }
+  }
+  // clamped offsets along each axis, and their contribution to the address
+  int64_t off[ND][5];
+#pragma unroll
+  for (int i = 0; i < ND; ++i)
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) off[i][d + 2] = (int64_t)min(max(s[i] + d, 0), g.n[i] - 1) * g.st[i];
+  T P[P5][CC];
+#pragma unroll
+  for (int e = 0; e < P5; ++e) {
+    int twos = 0;
+    int64_t a = 0;
+#pragma unroll
+    for (int i = 0, r = e; i < ND; ++i, r /= 5) {
+      twos += (r % 5 == 0 || r % 5 == 4) ? 1 : 0;
+      a += off[i][r % 5];
+    }
+    if (twos > 1) continue;  // no gradient reads it
+#pragma unroll
+    for (int c = 0; c < CC; ++c) P[e][c] = img[a * CC + c];
+  }
+  auto grad = [&](int o) {  // o: index of the offset in {-1,0,1}^ND, axis 0 fastest
+    int pe = 0;
+#pragma unroll
+    for (int i = 0, r = o, m = 1; i < ND; ++i, r /= 3, m *= 5) pe += (r % 3 + 1) * m;
+    G acc = 0;
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+#pragma unroll
+      for (int i = 0, m = 1; i < ND; ++i, m *= 5) {
+        const G a = (G)P[pe + m][c], b = (G)P[pe - m][c];
+        if constexpr (std::is_same<G, double>::value) {
+#pragma clang fp contract(off)
+          const double d = a - b;
+          acc = acc + d * d;
+        } else {
+          acc += (a - b) * (a - b);
+        }
+      }
+    }
+    return acc;
+  };
+  constexpr int kSelf = (N3 - 1) / 2;  // offset 0 on every axis
+  G gb = grad(kSelf);
+  int best = kSelf;
+#pragma unroll
+  for (int o = 0; o < N3; ++o) {
+    bool inside = true;
+#pragma unroll
+    for (int i = 0, r = o; i < ND; ++i, r /= 3) {
+      const int q = s[i] + r % 3 - 1;
+      inside = inside && q >= 0 && q < g.n[i];
+    }
+    const G v = grad(o);
+    if (inside && v < gb) {
+      gb = v;
+      best = o;
+    }
+  }
+  int64_t bl = 0;
+  int bq[ND];
+#pragma unroll
+  for (int i = 0, r = best; i < ND; ++i, r /= 3) {
+    bq[i] = s[i] + r % 3 - 1;
+    bl += (int64_t)bq[i] * g.st[i];
+  }
+  double* row = cen + k * g.row;
+  for (int c = 0; c < CC; ++c) row[c] = (double)img[bl * CC + c];
+  for (int i = 0; i < g.nd_out; ++i) row[CC + i] = (double)bq[i];
+}
+
 // Calls f(descriptor) for the lanes with `in`.  A wave whose lanes all work
 // on one image (the common case: images hold many clusters) reads that
 // image's descriptor through scalar loads; a mixed wave reads it per lane.
@@ -589,8 +681,34 @@ hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) { re
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) { return fill(p, v, n, s); }
 
+template <typename T, int ND>
+bool seed_fixed_c(const Geo& g, const void* img, double* cen, hipStream_t s) {
+  const int nb = blocks_for(g.K);
+  const T* p = (const T*)img;
+  switch (g.C) {
+    case 1: seed_fixed_kernel<T, ND, 1><<<nb, kThreads, 0, s>>>(g, p, cen); return true;
+    case 3: seed_fixed_kernel<T, ND, 3><<<nb, kThreads, 0, s>>>(g, p, cen); return true;
+    case 4: seed_fixed_kernel<T, ND, 4><<<nb, kThreads, 0, s>>>(g, p, cen); return true;
+    default: return false;
+  }
+}
+
+template <typename T>
+bool seed_fixed(const Geo& g, const void* img, double* cen, hipStream_t s) {
+  if (g.nd == 2) return seed_fixed_c<T, 2>(g, img, cen, s);
+  if (g.nd == 3) return seed_fixed_c<T, 3>(g, img, cen, s);
+  return false;
+}
+
 hipError_t launch_seed(const Geo& g, const void* img, double* cen, hipStream_t s) {
   int nb = blocks_for(g.K);
+  bool done = false;
+  switch (g.dtype) {
+    case kU8: done = seed_fixed<uint8_t>(g, img, cen, s); break;
+    case kU16: done = seed_fixed<uint16_t>(g, img, cen, s); break;
+    default: done = seed_fixed<float>(g, img, cen, s); break;
+  }
+  if (done) return hipGetLastError();
   switch (g.dtype) {
     case kU8: seed_kernel<uint8_t><<<nb, kThreads, 0, s>>>(g, (const uint8_t*)img, cen); break;
     case kU16: seed_kernel<uint16_t><<<nb, kThreads, 0, s>>>(g, (const uint16_t*)img, cen); break;
