@@ -488,24 +488,51 @@ __device__ __forceinline__ void finalize_one(const Geo& g, double* __restrict__ 
         any = any && lo[i] <= hi[i];
         t0[i] = lo[i] / tdT[i];
       }
+      constexpr int NQ = 1 << ND;
+      uint32_t qm = 0;  // the slots of the tiles the window meets
       if (any) {
 #pragma unroll
-        for (int q = 0; q < (1 << ND); ++q) {
+        for (int q = 0; q < NQ; ++q) {
           bool meets = true;
 #pragma unroll
           for (int i = 0; i < ND; ++i) {
             if ((q >> i) & 1) meets = meets && (t0[i] + 1) * tdT[i] <= hi[i];
           }
-          if (!meets) continue;
-          const uint64_t* p = it.part + (k * (1 << ND) + q) * (F + 1);
-          if (p[F] != (uint64_t)(t + 1)) continue;  // not written this iteration
+          if (meets) qm |= 1u << q;
+        }
+      }
+      auto add_slot = [&](const uint64_t* w) {
 #pragma unroll
-          for (int f = 0; f < 1 + ND; ++f) si[f] += p[f];
-          for (int c = 0; c < C; ++c) {
-            const uint64_t raw = p[1 + ND + c];
-            if (FLT) sf[c] += __longlong_as_double((long long)raw);
-            else sc[c] += raw;
-          }
+        for (int f = 0; f < 1 + ND; ++f) si[f] += w[f];
+        for (int c = 0; c < C; ++c) {
+          const uint64_t raw = w[1 + ND + c];
+          if (FLT) sf[c] += __longlong_as_double((long long)raw);
+          else sc[c] += raw;
+        }
+      };
+      if constexpr (ND <= 3) {
+        // every meeting slot's words and tag in flight at once, then the
+        // slots written this iteration are added in slot order
+        constexpr int FW = 1 + ND + CM;
+        uint64_t w[NQ][FW + 1];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (!((qm >> q) & 1u)) continue;
+          const uint64_t* p = it.part + (k * NQ + q) * (F + 1);
+          w[q][FW] = p[F];
+#pragma unroll
+          for (int f = 0; f < 1 + ND; ++f) w[q][f] = p[f];
+          for (int c = 0; c < C; ++c) w[q][1 + ND + c] = p[1 + ND + c];
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (((qm >> q) & 1u) && w[q][FW] == (uint64_t)(t + 1)) add_slot(w[q]);
+      } else {
+        for (int q = 0; q < NQ; ++q) {
+          if (!((qm >> q) & 1u)) continue;
+          const uint64_t* p = it.part + (k * NQ + q) * (F + 1);
+          if (p[F] != (uint64_t)(t + 1)) continue;  // not written this iteration
+          add_slot(p);
         }
       }
     }
