@@ -36,15 +36,29 @@ __device__ __forceinline__ int find_root(const int32_t* parent, int v) {
   return v;
 }
 
-// Lock-free union: always hang the larger root under the smaller one, so a
-// root is the smallest index of its set.
-__device__ __forceinline__ void unite(int32_t* parent, int a, int b) {
+// Lock-free union of the sets of two nodes of the forest of local roots
+// (after the local pass every voxel points at its local root, and only local
+// roots are ever linked): the larger root hangs under the smaller one, so a
+// root is the smallest index of its set.  Paths are halved on the way with
+// plain stores: a halving store writes a local root's parent, never another
+// voxel's, and only moves it toward its root.
+__device__ __forceinline__ int find_halving(int32_t* parent, int v) {
   while (true) {
-    a = find_root(parent, a);
-    b = find_root(parent, b);
+    const int p = parent[v];
+    const int gp = parent[p];
+    if (p == gp) return p;
+    parent[v] = gp;
+    v = gp;
+  }
+}
+
+__device__ __forceinline__ void unite_roots(int32_t* parent, int a, int b) {
+  while (true) {
+    a = find_halving(parent, a);
+    b = find_halving(parent, b);
     if (a == b) return;
     if (a < b) {
-      int t = a;
+      const int t = a;
       a = b;
       b = t;
     }
@@ -233,6 +247,12 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   }
 }
 
+// Unions across the low face x_i = o_i of every tile, on the global parents.
+// The face is walked with the first other axis fastest, one voxel per lane;
+// a pair equal to the pair one step before it along that axis (same label
+// on both sides) is already joined through it, since each side's pair of
+// voxels lies in one local component, so only the first pair of each such
+// overlap unites.
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
@@ -240,12 +260,13 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   tile_origin<ND>(g, blockIdx.x, o);
   for (int i = 0; i < ND; ++i) {
     if (o[i] == 0) continue;
-    // the face x_i = o_i: 4096 >> L[i] voxels, the other axes in raster order
     const int nf = kTileVox >> CCTile<ND>::L[i];
-    for (int f = threadIdx.x; f < nf; f += kThreads) {
+    const int ea = 1 << CCTile<ND>::L[i == 0 ? 1 : 0];  // extent of the fastest face axis
+    for (int f0 = 0; f0 < nf; f0 += kThreads) {
+      const int f = f0 + (int)threadIdx.x;
       int r = f;
       int64_t v = 0;
-      bool in = true;
+      bool in = f < nf;
       for (int a = 0; a < ND; ++a) {
         int xa;
         if (a == i) {
@@ -257,9 +278,12 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
         in = in && xa < g.n[a];
         v += (int64_t)xa * g.st[a];
       }
-      if (!in) continue;
       const int64_t u = v - g.st[i];
-      if (labels[u] == labels[v]) unite(b.parent, (int)u, (int)v);
+      const int lv = in ? labels[v] : -1, lu = in ? labels[u] : -2;
+      // the pair one step before along the fastest face axis (the lane before)
+      const int pv = __shfl_up(lv, 1, 64), pu = __shfl_up(lu, 1, 64);
+      const bool first = f % ea == 0 || pv != lv || pu != lu;
+      if (in && lu == lv && first) unite_roots(b.parent, b.parent[u], b.parent[v]);
     }
   }
 }
