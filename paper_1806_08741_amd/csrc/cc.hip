@@ -174,15 +174,19 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     }
   }
   __syncthreads();
-  // every thread walks kSeg consecutive voxels of one row along axis 0:
+  // every thread walks kSeg consecutive voxels of one row along axis 0, with
+  // their labels in registers (LDS reads issued together, not one per test):
   // runs of equal labels point at their first voxel (no atomics) ...
   const int j0 = threadIdx.x * kSeg;
+  int own[kSeg];
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) own[q] = s_lab[pd(j0 + q)];
   {
     int start = j0;
+#pragma unroll
     for (int q = 1; q < kSeg; ++q) {
-      const int j = j0 + q;
-      if (s_lab[pd(j)] != s_lab[pd(j - 1)]) start = j;
-      s_par[pd(j)] = start;
+      if (own[q] != own[q - 1]) start = j0 + q;
+      s_par[pd(j0 + q)] = start;
     }
   }
   __syncthreads();
@@ -191,24 +195,37 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   {
     int x0[ND];
     local_coords(j0, x0);
-    if (x0[0] > 0 && s_lab[pd(j0)] >= 0 && s_lab[pd(j0)] == s_lab[pd(j0 - 1)])
-      unite_local(s_par, j0 - 1, j0);
+    if (x0[0] > 0 && own[0] >= 0 && own[0] == s_lab[pd(j0 - 1)]) unite_local(s_par, j0 - 1, j0);
     int sh = CCTile<ND>::L[0];
+#pragma unroll
     for (int i = 1; i < ND; ++i) {
       if (x0[i] > 0) {
         const int d = 1 << sh;
+        int below[kSeg];
+#pragma unroll
+        for (int q = 0; q < kSeg; ++q) below[q] = s_lab[pd(j0 + q - d)];
+#pragma unroll
         for (int q = 0; q < kSeg; ++q) {
-          const int j = j0 + q, l = s_lab[pd(j)];
-          if (l < 0 || s_lab[pd(j - d)] != l) continue;
-          if (q > 0 && s_lab[pd(j - 1)] == l && s_lab[pd(j - 1 - d)] == l) continue;  // same pair of runs
-          unite_local(s_par, j - d, j);
+          const int l = own[q];
+          if (l < 0 || below[q] != l) continue;
+          if (q > 0 && own[q - 1] == l && below[q - 1] == l) continue;  // same pair of runs
+          unite_local(s_par, j0 + q - d, j0 + q);
         }
       }
       sh += CCTile<ND>::L[i];
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < kTileVox; j += kThreads) s_par[pd(j)] = find_local(s_par, j);
+  {  // every voxel to its local root (first steps read together)
+    int p[kSeg];
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) p[q] = s_par[pd(threadIdx.x + q * kThreads)];
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      const int j = threadIdx.x + q * kThreads;
+      if (p[q] != j) s_par[pd(j)] = find_local(s_par, p[q]);
+    }
+  }
   __syncthreads();
   // labels are no longer needed: voxels outside the image get parent -1 and
   // the label words become the size counters
@@ -217,16 +234,17 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     s_size[pd(j)] = 0;
   }
   __syncthreads();
-  {  // sizes: each thread counts 16 consecutive voxels, one atomic per run
-    const int j0 = threadIdx.x * (kTileVox / kThreads);
+  {  // sizes: each thread counts its 16 consecutive voxels, one atomic per run
+    int r[kSeg];
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) r[q] = s_par[pd(j0 + q)];
     int cur = -1, n = 0;
-    for (int q = 0; q < kTileVox / kThreads; ++q) {
-      const int j = j0 + q;
-      if (s_par[pd(j)] < 0) continue;
-      const int r = s_par[pd(j)];
-      if (r != cur) {
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      if (r[q] < 0) continue;
+      if (r[q] != cur) {
         if (n) atomicAdd(&s_size[pd(cur)], n);
-        cur = r;
+        cur = r[q];
         n = 0;
       }
       ++n;
