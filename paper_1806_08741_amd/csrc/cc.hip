@@ -313,8 +313,7 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_flatten_kernel(Geo g, CCBuf b) {
-  __shared__ int s_root[kTileVox];
-  __shared__ uint32_t s_isr[kTileVox / 32];  // local roots
+  __shared__ int s_root[kTileVox];  // global root, at the local roots' entries
   int o[ND];
   tile_origin<ND>(g, blockIdx.x, o);
   int64_t base = 0;
@@ -323,8 +322,6 @@ cc_flatten_kernel(Geo g, CCBuf b) {
     base += (int64_t)o[i] * g.st[i];
     inv[i] = 1.0f / (float)g.st[i];
   }
-  for (int j = threadIdx.x; j < kTileVox / 32; j += kThreads) s_isr[j] = 0;
-  __syncthreads();
   auto voxel = [&](int j, int64_t& v) {
     int sh = 0;
     bool in = true;
@@ -353,7 +350,6 @@ cc_flatten_kernel(Geo g, CCBuf b) {
     voxel(j, v);
     const int r = par[q] == (int)v ? (int)v : find_root(b.parent, (int)v);
     s_root[j] = r;
-    atomicOr(&s_isr[j >> 5], 1u << (j & 31));
     if (r != (int)v) atomicAdd(&b.size[r], sz[q]);  // a local root joins its global root
     par[q] = -1;
   }
