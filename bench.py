@@ -39,10 +39,10 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 BYTES = {"u8": 1, "u16": 2, "f32": 4}
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from profiles/traffic_<kernel>_<workload>.json, if
-    the counters were taken on the current source of that kernel."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def load_profile(kind: str, kernel: str, workload: str):
+    """profiles/<kind>_<kernel>_<workload>.json, if its counters were taken on
+    the current code of that kernel, else None."""
+    path = os.path.join(ROOT, "profiles", f"{kind}_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -50,7 +50,30 @@ def load_traffic(kernel: str, workload: str):
     from paper_1806_08741_amd.profsum import kernel_source_hash
     if rec.get("source_hash") != kernel_source_hash(kernel):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the traffic record (see load_profile)."""
+    rec = load_profile("traffic", kernel, workload)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def copy_rate_gbs(mib: int = 1024, reps: int = 10) -> float:
+    """Device-to-device copy rate (bytes read + written per second), the
+    achievable line beside the 8 TB/s peak."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del a, b
+    return 2 * (mib << 20) * reps / dt / 1e9
 
 
 def cpu_baseline(img_gpu, w, crop):
@@ -213,6 +236,51 @@ def bench_served(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_contours(args, base: str):
+    """The contour mask (sslic_mask_contours) over a whole image of workload
+    ``base`` (slide-16k or fibsem-1k), on the labels of one run of it: the
+    image and labels are read once, the masked image written once."""
+    import torch
+    from paper_1806_08741_amd import sslic, synth
+
+    w = synth.WORKLOADS[base]
+    print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
+    img = synth.workload_image(w.name, "cuda")
+    ctx = sslic.Context(0)
+    lab = ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity)["labels"]
+    out = torch.empty_like(img)
+    for _ in range(args.warmup):
+        ctx.mask_contours(img, lab, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        ctx.mask_contours(img, lab, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    dt_name = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}[w.dtype]
+    N = w.voxels
+    per_vox = 4 + 2 * w.channels * BYTES[dt_name]
+    gbs = N * per_vox / (ms * 1e-3) / 1e9
+    print(f"[bench] mask_contours {ms:.4f} ms, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    rec = {
+        "metric": "contour mask Gvoxel/s (whole image per step; inputs resident in HBM)",
+        "value": round(N / (ms * 1e-3) / 1e9, 2), "unit": "Gvoxel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dt_name, "data": "synthetic",
+        "config": {"workload": f"contours-{base}", "dims": list(w.dims), "channels": w.channels,
+                   "image_dtype": dt_name, "labels": f"one {w.iterations}-iteration run"},
+        "roofline": {"bound": "hbm", "kernel": "mask_contours", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("contours", f"contours-{base}"),
+                     "algorithmic_bytes_per_launch": N * per_vox,
+                     "hbm_achievable_copy": round(copy_rate_gbs(), 1)},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +309,8 @@ def main():
         return bench_batch(args, int(args.workload.split("-")[1]))
     if args.workload == "served":
         return bench_served(args)
+    if args.workload.startswith("contours-"):
+        return bench_contours(args, args.workload.split("-", 1)[1])
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
@@ -294,6 +364,10 @@ def main():
 
     ms_step = dt / args.steps * 1e3
     value = N * w.iterations * args.steps / dt / 1e6
+    # the iteration loop alone (bin sort, sweep, reduce step over every iteration)
+    loop_ms = sum(prof[k]["ms_total"] for k in ("bins", "sweep", "finalize") if k in prof) / args.steps
+    copy_gbs = copy_rate_gbs()
+    valu = load_profile("valu", "sweep", w.name)
     dt_name = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}[w.dtype]
     # the sweep (assignment + map step) reads the image once and writes the labels once
     per_vox = w.channels * BYTES[dt_name] + 4
@@ -335,7 +409,12 @@ def main():
                      "flops_per_voxel": round(flops_vox, 2),
                      "hbm_achieved": round(achieved, 1), "hbm_peak": HBM_PEAK_GBS,
                      "hbm_unit": "GB/s", "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "hbm_achievable_copy": round(copy_gbs, 1),
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "valu_busy": None if valu is None else valu.get("valu_busy")},
+        "stages": {"iteration_loop": {"Mvoxel_iter_s": round(N * w.iterations / loop_ms / 1e3, 1),
+                                      "ms_per_run": round(loop_ms, 4)},
+                   "end_to_end": {"Mvoxel_iter_s": round(value, 1), "ms_per_run": round(ms_step, 4)}},
         "kernels_ms": {k: round(v["ms_mean"], 4) for k, v in prof.items()},
     }
     crop = args.cpu_crop if args.cpu_crop >= 0 else (4096 if len(w.dims) == 2 else 224)

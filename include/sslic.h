@@ -105,7 +105,7 @@ int sslic_num_clusters(int ndim, const int64_t* dims, const int32_t* S, int64_t*
  *   n_labels_out, iters_done_out  host or NULL; either one makes the call
  *              wait for `stream`.
  * Scratch: the context's workspace grows to about
- *   K * (64 + 8 (channels + ndim + 1)) + 4 ceil-bins + (connectivity ? 13 N : 0)
+ *   K * (64 + 8 (channels + ndim + 1) (1 + 2^ndim)) + 4 ceil-bins + (connectivity ? 16 N : 0)
  * bytes and is reused across calls. */
 int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
               int channels, sslic_dtype dtype, const int32_t* S, double m, int iterations,
@@ -131,9 +131,9 @@ typedef struct {
 
 /* Many independent images in one pass (the batched form).  Images may differ
  * in size, ndim, channels, dtype, S, m and iterations.  Seeding, then the
- * iterations of every image interleaved: per iteration one persistent launch
- * per group of images sharing (dtype, ndim, channels, tile shape) walks a
- * flat work-list of their tiles; each image stops on its own residual test
+ * iterations of every image interleaved: per iteration one launch per group
+ * of images sharing (dtype, ndim, channels, tile shape) covers a flat
+ * work-list of their tiles, one workgroup per tile; each image stops on its own residual test
  * (opt->tol) or after its own `iterations`; then connectivity per image
  * unless opt->no_connectivity.  Each image's result is the one sslic_run
  * gives for it alone (bit-identical labels and centres for integer images;
@@ -150,6 +150,21 @@ typedef struct {
  * n_labels_out: host int32 [n] or NULL (makes the call wait). */
 int sslic_run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n,
                     const sslic_options* opt, int32_t* n_labels_out, sslic_stream_t stream);
+
+/* The superpixel contour mask the paper renders its results with (Sec. 4,
+ * visualisation: the image masked by the label contour): a voxel lies on a
+ * contour when one of its 2 ndim face neighbours inside the image carries a
+ * different label (neighbours outside the image do not count).  out = image
+ * with every contour voxel set to 0 in all channels, every other voxel
+ * copied.
+ *   image   device, N * channels elements of `dtype` (as for sslic_run)
+ *   labels  device int32 [N], any values
+ *   out     device, N * channels elements of `dtype`; must not overlap image
+ * Enqueued on `stream`; uses no workspace.  Returns SSLIC_EINVAL for bad
+ * sizes or NULL pointers (nothing enqueued). */
+int sslic_mask_contours(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
+                        int channels, sslic_dtype dtype, const int32_t* labels, void* out,
+                        sslic_stream_t stream);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char* sslic_last_error(void);

@@ -66,6 +66,7 @@ def _load():
         lib.or_update.argtypes = [P, I, P, I, I, P, D, P, I64, P, P, P]
         lib.or_connectivity.argtypes = [I, P, P, P, I, I64, P, P]
         lib.or_run.argtypes = [P, I, P, I, I, P, D, I, D, I, P, P, P, P, P, P, P]
+        lib.or_mask_contours.argtypes = [P, I, P, I, I, P, P]
         _lib = lib
     return _lib
 
@@ -172,6 +173,16 @@ def connectivity(dims, S, centres, C, labels):
     _check(_load().or_connectivity(len(dims), _ptr(dims), _ptr(S), _ptr(centres), C,
                                    centres.shape[0], _ptr(labels), _ptr(nl)))
     return int(nl[0])
+
+
+def mask_contours(img, ndim, labels):
+    """The image with its label contours set to 0 (same shape and dtype)."""
+    img, dims, C, dt = _geom(img, ndim)
+    labels = np.ascontiguousarray(labels, dtype=np.int32).reshape(-1)
+    assert labels.size == int(np.prod(dims))
+    out = np.empty_like(img)
+    _check(_load().or_mask_contours(_ptr(img), ndim, _ptr(dims), C, dt, _ptr(labels), _ptr(out)))
+    return out
 
 
 def run(img, ndim, S, m, iterations, tol=0.0, connectivity=True, init_centres=None):

@@ -426,6 +426,24 @@ int sslic_connectivity(sslic_ctx* ctx, int ndim, const int64_t* dims, const int3
   return read_ints(ctx, s, nl, n_labels_out, nullptr, nullptr);
 }
 
+int sslic_mask_contours(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
+                        int channels, sslic_dtype dtype, const int32_t* labels, void* out,
+                        sslic_stream_t stream) {
+  if (!ctx || !image || !labels || !out) return fail(SSLIC_EINVAL, "missing pointer");
+  if (ndim < 1 || ndim > kMaxDim || !dims) return fail(SSLIC_EINVAL, "ndim %d outside [1, 4]", ndim);
+  int32_t S[kMaxDim];
+  for (int i = 0; i < ndim; ++i) S[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(dims[i], 1), 1 << 30);
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, 1.0, 0);
+  if (rc) return rc;
+  const size_t bytes = (size_t)g.N * channels * (dtype == kU8 ? 1 : dtype == kU16 ? 2 : 4);
+  const char *a = (const char*)image, *o = (const char*)out;
+  if (a < o + bytes && o < a + bytes) return fail(SSLIC_EINVAL, "out overlaps image");
+  if ((rc = select_device(ctx))) return rc;
+  HIP_TRY(launch_mask_contours(g, image, labels, out, (hipStream_t)stream));
+  return SSLIC_OK;
+}
+
 int sslic_profile_enable(sslic_ctx* ctx, int enable) {
   if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
   int rc = select_device(ctx);

@@ -206,6 +206,9 @@ inline void cc_carve(CCBuf& c, int32_t* region, int64_t N) {
   c.brpart = region + 2 * nc + nb;
   c.nroots = region + 2 * nc + 2 * nb;
 }
+// the image with its label contours set to 0 (out may not alias img)
+hipError_t launch_mask_contours(const Geo& g, const void* img, const int32_t* labels, void* out,
+                                hipStream_t s);
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
                                const CCBuf& b, int32_t* n_labels_dev, hipStream_t s);
 

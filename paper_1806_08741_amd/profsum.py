@@ -39,6 +39,7 @@ KERNELS = {
     "finalize": (r"finalize_kernel", ["centres.hip", "sslic_internal.h"]),
     "seed": (r"seed_kernel", ["centres.hip", "sslic_internal.h"]),
     "update": (r"update_kernel", ["update.hip", "sslic_internal.h"]),
+    "contours": (r"mask_contours_kernel", ["contours.hip", "sslic_internal.h"]),
 }
 
 

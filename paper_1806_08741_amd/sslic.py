@@ -71,9 +71,10 @@ def lib():
             L.sslic_assign.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P]
             L.sslic_update.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P, P, P]
             L.sslic_connectivity.argtypes = [P, I, P, P, I, P, I64, P, P, P, P]
+            L.sslic_mask_contours.argtypes = [P, P, I, P, I, I, P, P, P]
             for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_batch",
                          "sslic_seed", "sslic_grid_labels", "sslic_assign", "sslic_update",
-                         "sslic_connectivity"):
+                         "sslic_connectivity", "sslic_mask_contours"):
                 getattr(L, name).restype = I
             _lib = L
     return _lib
@@ -288,6 +289,20 @@ class Context:
                                   _ptr(labels), K, _ptr(cen), _ptr(counts), _ptr(res),
                                   _stream(img.device)))
         return cen, counts, res
+
+    def mask_contours(self, img: torch.Tensor, labels: torch.Tensor,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The image with its label contours set to 0 (``sslic_mask_contours``)."""
+        nd, dims, C, dt = _geom(img)
+        if labels.device != img.device or labels.dtype != torch.int32 or not labels.is_contiguous():
+            raise SslicError("labels must be a contiguous int32 tensor on the image's device")
+        if labels.numel() != img.numel() // C:
+            raise SslicError("labels must hold one entry per voxel")
+        if out is None:
+            out = torch.empty_like(img)
+        _check(lib().sslic_mask_contours(self._h, _ptr(img), nd, _i64(dims), C, dt,
+                                         _ptr(labels), _ptr(out), _stream(img.device)))
+        return out
 
     def connectivity(self, dims, S, centres: torch.Tensor, C: int, labels: torch.Tensor) -> int:
         """Connectivity enforcement in place on ``labels``; returns n_labels."""
