@@ -281,6 +281,46 @@ def bench_contours(args, base: str):
     print(json.dumps(rec), flush=True)
 
 
+def bench_lab(args):
+    """RGB to CIE-Lab (sslic_rgb_to_lab) over the 16384x16384 slide-like RGB
+    image: 3 bytes read and 12 written per pixel."""
+    import torch
+    from paper_1806_08741_amd import sslic, synth
+
+    w = synth.WORKLOADS["slide-16k"]
+    print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
+    img = synth.workload_image(w.name, "cuda")
+    ctx = sslic.Context(0)
+    out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+    for _ in range(args.warmup):
+        ctx.rgb_to_lab(img, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        ctx.rgb_to_lab(img, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    N = w.voxels
+    gbs = N * 15 / (ms * 1e-3) / 1e9
+    print(f"[bench] rgb_to_lab {ms:.4f} ms, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    rec = {
+        "metric": "RGB to CIE-Lab Gpixel/s (whole image per step; inputs resident in HBM)",
+        "value": round(N / (ms * 1e-3) / 1e9, 2), "unit": "Gpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "lab-16k", "dims": list(w.dims), "input": "u8 RGB", "output": "f32 Lab"},
+        "roofline": {"bound": "hbm", "kernel": "rgb_to_lab", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("lab", "lab-16k"),
+                     "algorithmic_bytes_per_launch": N * 15,
+                     "hbm_achievable_copy": round(copy_rate_gbs(), 1)},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,6 +351,8 @@ def main():
         return bench_served(args)
     if args.workload.startswith("contours-"):
         return bench_contours(args, args.workload.split("-", 1)[1])
+    if args.workload == "lab-16k":
+        return bench_lab(args)
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
     print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)

@@ -166,6 +166,20 @@ int sslic_mask_contours(sslic_ctx* ctx, const void* image, int ndim, const int64
                         int channels, sslic_dtype dtype, const int32_t* labels, void* out,
                         sslic_stream_t stream);
 
+/* RGB to CIE-Lab, the colour space the paper's colour runs use (Sec. 2.1;
+ * Sec. 4 converts its 8-bit RGB data to float Lab; the default m = 10
+ * assumes it).  Input: 8-bit sRGB; output: L in [0, 100], a, b, as floats.
+ * Conversion: the sRGB transfer curve, the four-digit sRGB-to-XYZ matrix and
+ * the D65 white (0.95047, 1, 1.08883), then the CIE Lab function (epsilon =
+ * 216/24389, kappa = 24389/27); with these constants the Lab ranges the
+ * paper prints for 8-bit RGB come out.
+ *   rgb  device uint8 [n_pixels][3]
+ *   lab  device float [n_pixels][3] (output); must not overlap rgb
+ * Enqueued on `stream`; uses no workspace.  Returns SSLIC_EINVAL for NULL
+ * pointers, n_pixels < 0 or overlapping buffers (nothing enqueued). */
+int sslic_rgb_to_lab(sslic_ctx* ctx, const uint8_t* rgb, int64_t n_pixels, float* lab,
+                     sslic_stream_t stream);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char* sslic_last_error(void);
 

@@ -67,6 +67,7 @@ def _load():
         lib.or_connectivity.argtypes = [I, P, P, P, I, I64, P, P]
         lib.or_run.argtypes = [P, I, P, I, I, P, D, I, D, I, P, P, P, P, P, P, P]
         lib.or_mask_contours.argtypes = [P, I, P, I, I, P, P]
+        lib.or_rgb_to_lab.argtypes = [P, I64, P]
         _lib = lib
     return _lib
 
@@ -173,6 +174,15 @@ def connectivity(dims, S, centres, C, labels):
     _check(_load().or_connectivity(len(dims), _ptr(dims), _ptr(S), _ptr(centres), C,
                                    centres.shape[0], _ptr(labels), _ptr(nl)))
     return int(nl[0])
+
+
+def rgb_to_lab(rgb):
+    """8-bit RGB (..., 3) to CIE-Lab (FP64, same shape)."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    assert rgb.shape[-1] == 3
+    out = np.empty(rgb.shape, dtype=np.float64)
+    _check(_load().or_rgb_to_lab(_ptr(rgb), rgb.size // 3, _ptr(out)))
+    return out
 
 
 def mask_contours(img, ndim, labels):

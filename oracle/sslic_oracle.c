@@ -566,6 +566,38 @@ int or_connectivity(int nd, const int64_t* dims, const int32_t* S,
 }
 
 /* ---------------------------------------------------------------------- */
+/* RGB to CIE-Lab (Sec. 2.1 and the data paragraph of Sec. 4: the colour
+ * runs work on Lab converted from 8-bit RGB).  Reading: 8-bit sRGB, the sRGB
+ * transfer curve, the four-digit sRGB-to-XYZ matrix, the D65 white
+ * (0.95047, 1, 1.08883) and the CIE Lab function; these constants give the
+ * ranges of L, a and b the paper prints for 8-bit RGB. */
+static double srgb_linear(double v) {
+  return v <= 0.04045 ? v / 12.92 : pow((v + 0.055) / 1.055, 2.4);
+}
+
+static double lab_fn(double t) {
+  const double eps = 216.0 / 24389.0, kappa = 24389.0 / 27.0;
+  return t > eps ? cbrt(t) : (kappa * t + 16.0) / 116.0;
+}
+
+int or_rgb_to_lab(const uint8_t* rgb, int64_t n, double* lab) {
+  if (n < 0) return OR_EINVAL;
+  for (int64_t p = 0; p < n; ++p) {
+    const double r = srgb_linear(rgb[3 * p] / 255.0);
+    const double g = srgb_linear(rgb[3 * p + 1] / 255.0);
+    const double b = srgb_linear(rgb[3 * p + 2] / 255.0);
+    const double X = 0.4124 * r + 0.3576 * g + 0.1805 * b;
+    const double Y = 0.2126 * r + 0.7152 * g + 0.0722 * b;
+    const double Z = 0.0193 * r + 0.1192 * g + 0.9505 * b;
+    const double fx = lab_fn(X / 0.95047), fy = lab_fn(Y / 1.0), fz = lab_fn(Z / 1.08883);
+    lab[3 * p] = 116.0 * fy - 16.0;
+    lab[3 * p + 1] = 500.0 * (fx - fy);
+    lab[3 * p + 2] = 200.0 * (fy - fz);
+  }
+  return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
 /* The contour mask the paper draws its superpixels with (Sec. 4, the
  * visualisation paragraph: the image is masked where the label contour is
  * non-zero).  Reading: a voxel is on the contour when one of its face

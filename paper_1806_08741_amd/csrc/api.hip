@@ -444,6 +444,20 @@ int sslic_mask_contours(sslic_ctx* ctx, const void* image, int ndim, const int64
   return SSLIC_OK;
 }
 
+int sslic_rgb_to_lab(sslic_ctx* ctx, const uint8_t* rgb, int64_t n_pixels, float* lab,
+                     sslic_stream_t stream) {
+  if (!ctx || !rgb || !lab) return fail(SSLIC_EINVAL, "missing pointer");
+  if (n_pixels < 0) return fail(SSLIC_EINVAL, "n_pixels = %lld < 0", (long long)n_pixels);
+  if (n_pixels == 0) return SSLIC_OK;
+  const char *a = (const char*)rgb, *o = (const char*)lab;
+  if (a < o + 12 * (size_t)n_pixels && o < a + 3 * (size_t)n_pixels)
+    return fail(SSLIC_EINVAL, "lab overlaps rgb");
+  int rc = select_device(ctx);
+  if (rc) return rc;
+  HIP_TRY(launch_rgb_to_lab(rgb, n_pixels, lab, (hipStream_t)stream));
+  return SSLIC_OK;
+}
+
 int sslic_profile_enable(sslic_ctx* ctx, int enable) {
   if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
   int rc = select_device(ctx);

@@ -206,6 +206,8 @@ inline void cc_carve(CCBuf& c, int32_t* region, int64_t N) {
   c.brpart = region + 2 * nc + nb;
   c.nroots = region + 2 * nc + 2 * nb;
 }
+// 8-bit sRGB pixels [n][3] to CIE-Lab floats [n][3]
+hipError_t launch_rgb_to_lab(const uint8_t* rgb, int64_t n, float* lab, hipStream_t s);
 // the image with its label contours set to 0 (out may not alias img)
 hipError_t launch_mask_contours(const Geo& g, const void* img, const int32_t* labels, void* out,
                                 hipStream_t s);

@@ -39,7 +39,8 @@ KERNELS = {
     "finalize": (r"finalize_kernel", ["centres.hip", "sslic_internal.h"]),
     "seed": (r"seed_kernel", ["centres.hip", "sslic_internal.h"]),
     "update": (r"update_kernel", ["update.hip", "sslic_internal.h"]),
-    "contours": (r"mask_contours_kernel", ["contours.hip", "sslic_internal.h"]),
+    "contours": (r"mask_contours", ["contours.hip", "sslic_internal.h"]),
+    "lab": (r"rgb_to_lab", ["lab.hip", "sslic_internal.h"]),
 }
 
 

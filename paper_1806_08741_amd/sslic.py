@@ -72,9 +72,10 @@ def lib():
             L.sslic_update.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P, P, P]
             L.sslic_connectivity.argtypes = [P, I, P, P, I, P, I64, P, P, P, P]
             L.sslic_mask_contours.argtypes = [P, P, I, P, I, I, P, P, P]
+            L.sslic_rgb_to_lab.argtypes = [P, P, I64, P, P]
             for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_batch",
                          "sslic_seed", "sslic_grid_labels", "sslic_assign", "sslic_update",
-                         "sslic_connectivity", "sslic_mask_contours"):
+                         "sslic_connectivity", "sslic_mask_contours", "sslic_rgb_to_lab"):
                 getattr(L, name).restype = I
             _lib = L
     return _lib
@@ -302,6 +303,18 @@ class Context:
             out = torch.empty_like(img)
         _check(lib().sslic_mask_contours(self._h, _ptr(img), nd, _i64(dims), C, dt,
                                          _ptr(labels), _ptr(out), _stream(img.device)))
+        return out
+
+    def rgb_to_lab(self, rgb: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """8-bit sRGB (..., 3) to CIE-Lab float32 of the same shape
+        (``sslic_rgb_to_lab``)."""
+        if not rgb.is_cuda or rgb.dtype != torch.uint8 or rgb.shape[-1] != 3 or \
+                not rgb.is_contiguous():
+            raise SslicError("rgb must be a contiguous uint8 (..., 3) tensor on a GPU")
+        if out is None:
+            out = torch.empty(rgb.shape, dtype=torch.float32, device=rgb.device)
+        _check(lib().sslic_rgb_to_lab(self._h, _ptr(rgb), rgb.numel() // 3, _ptr(out),
+                                      _stream(rgb.device)))
         return out
 
     def connectivity(self, dims, S, centres: torch.Tensor, C: int, labels: torch.Tensor) -> int:

@@ -93,3 +93,41 @@ def test_mask_contours_rejects_overlap(ctx):
     lab = dev(np.zeros(64 * 64, np.int32))
     with pytest.raises(sslic.SslicError):
         ctx.mask_contours(img, lab, out=img)
+
+
+# ---- RGB to CIE-Lab --------------------------------------------------------
+# FP32 arithmetic with a handful of roundings on values up to ~110, and the
+# a and b differences of cube roots near 1 scaled by 500 and 200: about 1e-4
+# at worst; the bar is ten times that.
+LAB_TOL = 1e-3
+
+
+def test_rgb_to_lab_all_colours(ctx):
+    rgb = np.stack(np.meshgrid(np.arange(256), np.arange(256), np.arange(256), indexing="ij"),
+                   -1).reshape(-1, 3).astype(np.uint8)
+    got = host(ctx.rgb_to_lab(dev(rgb)))
+    exp = oracle.rgb_to_lab(rgb)
+    assert np.abs(got - exp).max() <= LAB_TOL
+
+
+@pytest.mark.parametrize("n,offset", [(1, 0), (7, 0), (1001, 0), (4096, 1), (3333, 3)])
+def test_rgb_to_lab_ragged_and_unaligned(ctx, n, offset):
+    """Pixel counts off the 4-pixel groups, and buffers that are not aligned
+    for the word path (taken from an offset into a larger buffer)."""
+    rng = np.random.default_rng(n)
+    rgb = rng.integers(0, 256, size=(n + offset, 3)).astype(np.uint8)
+    d = dev(rgb)[offset:]
+    out = torch.empty((n + 1) * 3, dtype=torch.float32, device="cuda")[offset % 2:offset % 2 + 3 * n]
+    ctx.rgb_to_lab(d.contiguous() if offset == 0 else d, out=out.view(n, 3))
+    exp = oracle.rgb_to_lab(rgb[offset:])
+    assert np.abs(host(out).reshape(n, 3) - exp).max() <= LAB_TOL
+
+
+def test_rgb_to_lab_image_then_slic(ctx):
+    """A slide-like RGB image converted on the GPU and segmented in Lab, the
+    way the paper's colour runs work; the Lab image equals the oracle's."""
+    img = synth.workload_image("slide-16k", "cpu", dims=(512, 384)).numpy()
+    lab = ctx.rgb_to_lab(dev(img))
+    assert np.abs(host(lab) - oracle.rgb_to_lab(img)).max() <= LAB_TOL
+    r = ctx.run(lab, (16, 16), 10.0, 5, connectivity=True)
+    assert int(r["labels"].min()) >= 0 and int(r["labels"].max()) < r["n_labels"]

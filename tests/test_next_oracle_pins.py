@@ -77,3 +77,37 @@ def test_single_voxel_island(dims):
         exp = img.copy()
         exp[black] = 0
         np.testing.assert_array_equal(out, exp)
+
+
+# ---- RGB to CIE-Lab --------------------------------------------------------
+
+def all_colours_of_red(r):
+    g, b = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
+    return np.stack([np.full(g.size, r), g.reshape(-1), b.reshape(-1)], -1).astype(np.uint8)
+
+
+def test_lab_ranges_over_all_8bit_colours_are_the_printed_ones():
+    """The paper prints L in [0, 100], a in [-86.185, 98.254] and b in
+    [-107.863, 94.482] for 8-bit RGB in Lab (Sec. 2.1)."""
+    lo = np.full(3, np.inf)
+    hi = np.full(3, -np.inf)
+    for r in range(256):
+        lab = oracle.rgb_to_lab(all_colours_of_red(r))
+        lo = np.minimum(lo, lab.min(axis=0))
+        hi = np.maximum(hi, lab.max(axis=0))
+    np.testing.assert_allclose(lo, [0.0, -86.185, -107.863], atol=1e-3)
+    np.testing.assert_allclose(hi, [100.0, 98.254, 94.482], atol=1e-3)
+
+
+def test_lab_black_white_and_greys():
+    lab = oracle.rgb_to_lab(np.repeat(np.arange(256, dtype=np.uint8)[:, None], 3, axis=1))
+    np.testing.assert_array_equal(lab[0], [0.0, 0.0, 0.0])
+    assert abs(lab[255, 0] - 100.0) < 1e-9
+    assert np.abs(lab[:, 1:]).max() < 0.02       # greys are nearly neutral
+    assert np.all(np.diff(lab[:, 0]) > 0)        # lightness rises with the grey level
+
+
+def test_lab_of_pure_red():
+    """sRGB red is about (53.24, 80.09, 67.20) in Lab."""
+    lab = oracle.rgb_to_lab(np.array([[255, 0, 0]], np.uint8))[0]
+    np.testing.assert_allclose(lab, [53.24, 80.09, 67.20], atol=0.05)
