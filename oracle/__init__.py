@@ -65,7 +65,8 @@ def _load():
         lib.or_assign_points.argtypes = [P, I, P, I, I, P, D, P, I64, P, I64, P, P]
         lib.or_update.argtypes = [P, I, P, I, I, P, D, P, I64, P, P, P]
         lib.or_connectivity.argtypes = [I, P, P, P, I, I64, P, P]
-        lib.or_run.argtypes = [P, I, P, I, I, P, D, I, D, I, P, P, P, P, P, P, P]
+        lib.or_assign_persist.argtypes = [P, I, P, I, I, P, D, P, I64, P, P]
+        lib.or_run.argtypes = [P, I, P, I, I, P, D, I, D, I, I, P, P, P, P, P, P, P]
         lib.or_mask_contours.argtypes = [P, I, P, I, I, P, P]
         lib.or_rgb_to_lab.argtypes = [P, I64, P]
         _lib = lib
@@ -134,6 +135,21 @@ def assign(img, ndim, S, m, centres, labels):
     return labels
 
 
+def assign_persist(img, ndim, S, m, centres, labels, dist):
+    """One assignment step on a distance image kept between iterations:
+    ``labels`` (int32, N) and ``dist`` (float64 squared distances, N, +inf
+    where no centre has reached yet) are updated in place."""
+    img, dims, C, dt = _geom(img, ndim)
+    S = np.asarray(S, dtype=np.int32)
+    centres = np.ascontiguousarray(centres, dtype=np.float64)
+    assert labels.dtype == np.int32 and labels.flags.c_contiguous
+    assert dist.dtype == np.float64 and dist.flags.c_contiguous and dist.size == labels.size
+    _check(_load().or_assign_persist(_ptr(img), ndim, _ptr(dims), C, dt, _ptr(S), float(m),
+                                     _ptr(centres), centres.shape[0], _ptr(labels),
+                                     _ptr(dist)))
+    return labels, dist
+
+
 def assign_points(img, ndim, S, m, centres, points):
     """Labels (int32, -1 where no window holds the voxel) and least distances
     of the voxels at linear indices ``points``, each computed on its own over
@@ -195,9 +211,11 @@ def mask_contours(img, ndim, labels):
     return out
 
 
-def run(img, ndim, S, m, iterations, tol=0.0, connectivity=True, init_centres=None):
+def run(img, ndim, S, m, iterations, tol=0.0, connectivity=True, init_centres=None,
+        persist_distance=False):
     """The whole filter.  Returns a dict with labels (flat int32), centres,
-    counts, residuals, iterations run and n_labels."""
+    counts, residuals, iterations run and n_labels.  ``persist_distance``
+    keeps the distance image across iterations instead of resetting it."""
     img, dims, C, dt = _geom(img, ndim)
     S = np.asarray(S, dtype=np.int32)
     K, _ = num_clusters(dims, S)
@@ -213,8 +231,8 @@ def run(img, ndim, S, m, iterations, tol=0.0, connectivity=True, init_centres=No
         init = np.ascontiguousarray(init_centres, dtype=np.float64)
     _check(_load().or_run(_ptr(img), ndim, _ptr(dims), C, dt, _ptr(S), float(m),
                           int(iterations), float(tol), int(bool(connectivity)),
-                          _ptr(init), _ptr(labels), _ptr(cen), _ptr(counts), _ptr(res),
-                          _ptr(it), _ptr(nl)))
+                          int(bool(persist_distance)), _ptr(init), _ptr(labels), _ptr(cen),
+                          _ptr(counts), _ptr(res), _ptr(it), _ptr(nl)))
     return {"labels": labels, "centres": cen, "counts": counts,
             "residuals": res[: int(it[0])], "iterations": int(it[0]),
             "n_labels": int(nl[0])}

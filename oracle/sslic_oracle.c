@@ -25,7 +25,9 @@
  *     (Sec. 2.2 footnote on the Jacobian);
  *   - window: closed, |x_i - c_i| <= S_i, evaluated as the integer range
  *     [ceil(c_i - S_i), floor(c_i + S_i)] (Sec. 2.2, Sec. 3.1);
- *   - the distance image is reset to +inf at the start of every iteration;
+ *   - the distance image is reset to +inf at the start of every iteration
+ *     (or, with persist_distance, once before the first, as the original
+ *     SLIC loop of Sec. 2.2 initialises it);
  *     voxels no window covers keep their previous label, and before the
  *     first iteration every voxel carries the label of its grid cell;
  *   - equal distances: the lower cluster index wins (strict "<" while
@@ -256,19 +258,14 @@ int or_seed(const void* img, int nd, const int64_t* dims, int C, int dtype,
  * extended in Sec. 3.3; Sec. 2.2 / Sec. 3.1 stage 2: every centre scans its
  * window and keeps a per-voxel minimum distance and label). */
 
-int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
-              const int32_t* S, double m, const double* centres, int64_t K,
-              int32_t* labels) {
-  img_t g;
-  int rc = make_img(&g, img, nd, dims, C, dtype);
-  if (rc) return rc;
-  if (!(m > 0.0) || K < 1) return OR_EINVAL;
+/* The centre loop over the distance image d: every centre, in ascending k,
+ * visits the voxels of its window and takes each one whose d it beats. */
+static void assign_windows(const img_t* gp, int nd, int C, const int32_t* S, double m,
+                           const double* centres, int64_t K, int32_t* labels, double* d) {
+  const img_t g = *gp;
   const int row = C + nd;
   double w[OR_MAXD];
   for (int i = 0; i < nd; ++i) w[i] = (m * m) / ((double)S[i] * (double)S[i]);
-  double* d = (double*)malloc(sizeof(double) * (size_t)g.N);
-  if (!d) return OR_ENOMEM;
-  for (int64_t v = 0; v < g.N; ++v) d[v] = INFINITY; /* reset every iteration */
   int64_t lo[OR_MAXD], hi[OR_MAXD], x[OR_MAXD];
   for (int64_t k = 0; k < K; ++k) {
     const double* ck = centres + k * row;
@@ -309,7 +306,37 @@ int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
       if (i == nd) break;
     }
   }
+}
+
+int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
+              const int32_t* S, double m, const double* centres, int64_t K,
+              int32_t* labels) {
+  img_t g;
+  int rc = make_img(&g, img, nd, dims, C, dtype);
+  if (rc) return rc;
+  if (!(m > 0.0) || K < 1) return OR_EINVAL;
+  double* d = (double*)malloc(sizeof(double) * (size_t)g.N);
+  if (!d) return OR_ENOMEM;
+  for (int64_t v = 0; v < g.N; ++v) d[v] = INFINITY; /* reset every iteration */
+  assign_windows(&g, nd, C, S, m, centres, K, labels, d);
   free(d);
+  return OR_OK;
+}
+
+/* The same step on a distance image the caller keeps between iterations, as
+ * the original SLIC loop of Sec. 2.2 has it: d is set to infinity once,
+ * before the first iteration, and a voxel changes label only where some
+ * centre of this iteration comes strictly closer than the least distance it
+ * has seen so far.
+ *   dist  squared distances D^2 [N], read and updated in place */
+int or_assign_persist(const void* img, int nd, const int64_t* dims, int C, int dtype,
+                      const int32_t* S, double m, const double* centres, int64_t K,
+                      int32_t* labels, double* dist) {
+  img_t g;
+  int rc = make_img(&g, img, nd, dims, C, dtype);
+  if (rc) return rc;
+  if (!(m > 0.0) || K < 1 || !dist) return OR_EINVAL;
+  assign_windows(&g, nd, C, S, m, centres, K, labels, dist);
   return OR_OK;
 }
 
@@ -629,12 +656,15 @@ int or_mask_contours(const void* img, int nd, const int64_t* dims, int C, int dt
 /* ---------------------------------------------------------------------- */
 /* The whole filter: stage 1, the iterations of stage 2 and stage 3 (Sec. 3.1),
  * stopping early only when the residual drops below `tol` (Sec. 2.2
- * termination criterion; tol = 0 runs every iteration, as SSLIC does). */
+ * termination criterion; tol = 0 runs every iteration, as SSLIC does).  With
+ * persist_distance the distance image lives across the iterations (Sec. 2.2
+ * sets it to infinity once, before the loop). */
 
 int or_run(const void* img, int nd, const int64_t* dims, int C, int dtype,
            const int32_t* S, double m, int iterations, double tol, int connectivity,
-           const double* init_centres, int32_t* labels, double* centres,
-           int64_t* counts, double* residuals, int* iters_done, int32_t* n_labels) {
+           int persist_distance, const double* init_centres, int32_t* labels,
+           double* centres, int64_t* counts, double* residuals, int* iters_done,
+           int32_t* n_labels) {
   img_t g;
   int rc = make_img(&g, img, nd, dims, C, dtype);
   if (rc) return rc;
@@ -646,18 +676,29 @@ int or_run(const void* img, int nd, const int64_t* dims, int C, int dtype,
   if (init_centres) memcpy(centres, init_centres, sizeof(double) * (size_t)(K * row));
   else if ((rc = or_seed(img, nd, dims, C, dtype, S, centres))) return rc;
   or_grid_labels(nd, dims, S, labels);
+  double* dist = NULL;
+  if (persist_distance) {
+    dist = (double*)malloc(sizeof(double) * (size_t)g.N);
+    if (!dist) return OR_ENOMEM;
+    for (int64_t v = 0; v < g.N; ++v) dist[v] = INFINITY; /* once, before the loop */
+  }
   int t = 0;
   for (t = 0; t < iterations; ++t) {
-    if ((rc = or_assign(img, nd, dims, C, dtype, S, m, centres, K, labels))) return rc;
+    rc = dist ? or_assign_persist(img, nd, dims, C, dtype, S, m, centres, K, labels, dist)
+              : or_assign(img, nd, dims, C, dtype, S, m, centres, K, labels);
     double e = 0.0;
-    if ((rc = or_update(img, nd, dims, C, dtype, S, m, labels, K, centres, counts, &e)))
+    if (!rc) rc = or_update(img, nd, dims, C, dtype, S, m, labels, K, centres, counts, &e);
+    if (rc) {
+      free(dist);
       return rc;
+    }
     if (residuals) residuals[t] = e;
     if (e < tol) {
       ++t;
       break;
     }
   }
+  free(dist);
   if (iters_done) *iters_done = t;
   int32_t nl = (int32_t)K;
   if (connectivity) {

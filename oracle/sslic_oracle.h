@@ -27,6 +27,9 @@ int or_seed(const void* img, int nd, const int64_t* dims, int C, int dtype,
 int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
               const int32_t* S, double m, const double* centres, int64_t K,
               int32_t* labels);
+int or_assign_persist(const void* img, int nd, const int64_t* dims, int C, int dtype,
+                      const int32_t* S, double m, const double* centres, int64_t K,
+                      int32_t* labels, double* dist);
 int or_assign_points(const void* img, int nd, const int64_t* dims, int C, int dtype,
                      const int32_t* S, double m, const double* centres, int64_t K,
                      const int64_t* points, int64_t npts, int32_t* labels_out,
@@ -39,8 +42,9 @@ int or_connectivity(int nd, const int64_t* dims, const int32_t* S,
                     int32_t* n_labels);
 int or_run(const void* img, int nd, const int64_t* dims, int C, int dtype,
            const int32_t* S, double m, int iterations, double tol, int connectivity,
-           const double* init_centres, int32_t* labels, double* centres,
-           int64_t* counts, double* residuals, int* iters_done, int32_t* n_labels);
+           int persist_distance, const double* init_centres, int32_t* labels,
+           double* centres, int64_t* counts, double* residuals, int* iters_done,
+           int32_t* n_labels);
 
 #ifdef __cplusplus
 }

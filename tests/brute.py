@@ -53,6 +53,29 @@ def kmeans_assign(img, dims, S, m, centres, window=False, prev=None):
     return lab
 
 
+def kmeans_assign_persist(img, dims, S, m, centres, prev, dist):
+    """The windowed k-means step on a kept distance image: the least windowed
+    squared distance of each voxel replaces ``dist`` and its (first) argmin
+    replaces ``prev`` only where it is strictly below ``dist``.  Returns new
+    (labels, dist)."""
+    dims = list(dims)
+    n = len(dims)
+    C = img.shape[-1]
+    X = coords(dims).astype(np.float64)
+    scale = np.array([m / s for s in S], dtype=np.float64)
+    f = np.concatenate([features(img, dims), X * scale], 1)
+    g = np.concatenate([centres[:, :C], centres[:, C:] * scale], 1)
+    D = cdist(f, g, "sqeuclidean")
+    out = np.zeros(D.shape, dtype=bool)
+    for i in range(n):
+        out |= np.abs(X[:, i:i + 1] - centres[None, :, C + i]) > S[i]
+    D[out] = np.inf
+    best = D.min(1)
+    arg = np.argmin(D, 1).astype(np.int32)
+    take = best < dist
+    return np.where(take, arg, prev).astype(np.int32), np.where(take, best, dist)
+
+
 def bincount_update(img, dims, labels, centres):
     """Member means via numpy.bincount; empty clusters keep their centre."""
     K = centres.shape[0]

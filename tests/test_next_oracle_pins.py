@@ -1,10 +1,19 @@
 """Pins of the oracle's functions beyond the SLIC path proper: the contour
 mask of the paper's visualisation (Sec. 4), checked against closed forms of
-hand-built label images on 1 to 4 axes.  CPU only."""
+hand-built label images on 1 to 4 axes; the RGB to CIE-Lab conversion; and
+the assignment on a distance image kept across iterations (Sec. 2.2).  CPU
+only."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
+
+from tests import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 DTYPES = [np.uint8, np.uint16, np.float32]
 
@@ -111,3 +120,101 @@ def test_lab_of_pure_red():
     """sRGB red is about (53.24, 80.09, 67.20) in Lab."""
     lab = oracle.rgb_to_lab(np.array([[255, 0, 0]], np.uint8))[0]
     np.testing.assert_allclose(lab, [53.24, 80.09, 67.20], atol=0.05)
+
+
+# ---- distance image kept across iterations (Sec. 2.2) ----------------------
+
+def test_persist_golden_1d_separates_the_two_readings():
+    with open(os.path.join(GOLDEN, "persist_1d.json")) as fh:
+        gd = json.load(fh)
+    for dt in (np.uint8, np.float32):
+        img = np.array(gd["image"], dtype=dt).reshape(-1, 1)
+        init = np.array(gd["init_centres"], dtype=np.float64)
+        for mode, persist in (("reset", False), ("persist", True)):
+            r = oracle.run(img, 1, gd["S"], gd["m"], gd["iterations"], connectivity=False,
+                           init_centres=init, persist_distance=persist)
+            np.testing.assert_array_equal(r["labels"], gd[mode]["labels"])
+            np.testing.assert_allclose(r["centres"], gd[mode]["centres"], rtol=1e-15, atol=1e-15)
+        assert r["residuals"][1] == gd["persist"]["residual_2"]
+
+
+def _integer_setup(dims, S, C, seed):
+    rng = np.random.default_rng(seed)
+    n = len(dims)
+    img = rng.integers(0, 256, size=tuple(dims[::-1]) + (C,)).astype(np.uint8)
+    K, Ka = oracle.num_clusters(dims, S)
+    init = np.zeros((K, C + n))
+    init[:, :C] = rng.integers(0, 256, (K, C))
+    grid = np.stack(np.meshgrid(*[(np.arange(k) + 0.5) * d / k for k, d in zip(Ka, dims)],
+                                indexing="ij"), -1).reshape(-1, n, order="F")
+    init[:, C:] = np.clip(np.floor(grid) + rng.integers(-1, 2, (K, n)), 0, np.array(dims) - 1)
+    return img, init, Ka
+
+
+@pytest.mark.parametrize("dims,S,m,C", [((40, 24), (8, 8), 8.0, 3), ((20, 16, 12), (4, 4, 4), 8.0, 1),
+                                        ((37, 29), (8, 8), 16.0, 2)])
+def test_persist_run_equals_brute_force(dims, S, m, C):
+    """The whole run with the kept distance image against a NumPy model of
+    windowed k-means whose per-voxel minimum persists."""
+    img, init, Ka = _integer_setup(dims, S, C, 11)
+    T = 5
+    r = oracle.run(img, len(dims), S, m, T, connectivity=False, init_centres=init,
+                   persist_distance=True)
+    lab = brute.grid_cell_labels(dims, Ka)
+    dist = np.full(lab.shape, np.inf)
+    cen = init.copy()
+    for _ in range(T):
+        lab, dist = brute.kmeans_assign_persist(img, dims, S, m, cen, lab, dist)
+        cen, cnt = brute.bincount_update(img, dims, lab, cen)
+    np.testing.assert_array_equal(r["labels"], lab)
+    np.testing.assert_array_equal(r["centres"], cen)
+    np.testing.assert_array_equal(r["counts"], cnt)
+    # the two readings really differ on these inputs
+    r0 = oracle.run(img, len(dims), S, m, T, connectivity=False, init_centres=init)
+    assert (r0["labels"] != r["labels"]).any()
+
+
+def test_persist_step_from_infinity_is_the_reset_step():
+    img, init, Ka = _integer_setup((33, 21), (6, 6), 3, 5)
+    lab0 = brute.grid_cell_labels((33, 21), Ka)
+    a = oracle.assign(img, 2, (6, 6), 10.0, init, lab0.copy())
+    b, d = oracle.assign_persist(img, 2, (6, 6), 10.0, init, lab0.copy(), np.full(lab0.size, np.inf))
+    np.testing.assert_array_equal(a, b)
+    _, dist = oracle.assign_points(img, 2, (6, 6), 10.0, init, np.arange(lab0.size))
+    np.testing.assert_array_equal(d, dist)
+
+
+def test_persist_step_invariants():
+    """d never grows; a label changes only where d fell; where d fell it is the
+    least windowed distance of this step and the label its first argmin."""
+    img, init, Ka = _integer_setup((30, 26), (5, 5), 1, 3)
+    lab = brute.grid_cell_labels((30, 26), Ka)
+    dist = np.full(lab.size, np.inf)
+    cen = init.copy()
+    for _ in range(4):
+        l0, d0 = lab.copy(), dist.copy()
+        lab, dist = oracle.assign_persist(img, 2, (5, 5), 6.0, cen, lab, dist)
+        assert np.all(dist <= d0)
+        fell = dist < d0
+        assert np.all(lab[~fell] == l0[~fell])
+        pl, pd = oracle.assign_points(img, 2, (5, 5), 6.0, cen, np.nonzero(fell)[0])
+        np.testing.assert_array_equal(lab[fell], pl)
+        np.testing.assert_array_equal(dist[fell], pd)
+        cen, _, _ = oracle.update(img, 2, (5, 5), 6.0, lab, cen)
+
+
+def test_persist_equals_reset_on_cell_images():
+    """On an image that is constant on its S-grid cells with strong contrast,
+    every voxel's nearest centre is its own cell's under either reading, so
+    the two runs agree."""
+    rng = np.random.default_rng(2)
+    dims, S = (48, 40), (8, 8)
+    K, Ka = oracle.num_clusters(dims, S)
+    vals = rng.permutation(K) * (250 // K) + 2
+    cell = brute.grid_cell_labels(dims, Ka)
+    img = vals[cell].astype(np.uint8).reshape(dims[::-1] + (1,))
+    a = oracle.run(img, 2, S, 10.0, 6, connectivity=False)
+    b = oracle.run(img, 2, S, 10.0, 6, connectivity=False, persist_distance=True)
+    np.testing.assert_array_equal(a["labels"], cell)
+    np.testing.assert_array_equal(b["labels"], a["labels"])
+    np.testing.assert_array_equal(b["centres"], a["centres"])
