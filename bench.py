@@ -17,6 +17,15 @@ connectivity).  Prints one JSON line:
                  rocprofv3 FETCH_SIZE/WRITE_SIZE counters when they were taken
                  on the current kernel source, else null
   cpu_baseline   the FP64 oracle (single thread) on a crop of the same image
+
+Other workloads (--workload): fibsem-1k (1024^3 uint16, connectivity on);
+persist-<workload> (the same run with the distance image kept across
+iterations, whose dominant kernel is the kept-distance assignment);
+batch-512 (the batched form against the same images one at a time); served
+(the serving loop, p50/p99 at two offered loads and closed-loop throughput);
+contours-<workload> (the contour mask over the image and the labels of one
+run); lab-16k (8-bit RGB to CIE-Lab over the 16384^2 image).  The last two are
+HBM-bound and report their roofline against 8 TB/s.
 """
 from __future__ import annotations
 
@@ -76,7 +85,7 @@ def copy_rate_gbs(mib: int = 1024, reps: int = 10) -> float:
     return 2 * (mib << 20) * reps / dt / 1e9
 
 
-def cpu_baseline(img_gpu, w, crop):
+def cpu_baseline(img_gpu, w, crop, persist=False):
     """The oracle as it stands, one thread, on the leading crop (side ``crop``
     on every axis) of the same image; returns (Mvoxel*iter/s, seconds,
     description)."""
@@ -85,7 +94,8 @@ def cpu_baseline(img_gpu, w, crop):
     sl = tuple(slice(0, min(crop, d)) for d in reversed(w.dims))
     sub = img_gpu[sl].contiguous().cpu().numpy()
     t0 = time.perf_counter()
-    r = oracle.run(sub, nd, w.S, w.m, w.iterations, connectivity=w.connectivity)
+    r = oracle.run(sub, nd, w.S, w.m, w.iterations, connectivity=w.connectivity,
+                   persist_distance=persist)
     dt = time.perf_counter() - t0
     vox = int(np.prod(sub.shape[:-1]))
     assert r["iterations"] == w.iterations
@@ -353,7 +363,11 @@ def main():
         return bench_contours(args, args.workload.split("-", 1)[1])
     if args.workload == "lab-16k":
         return bench_lab(args)
-    w = synth.WORKLOADS[args.workload]
+    # persist-<workload>: the literal loop of Sec. 2.2 and Sec. 3.1 (distance
+    # image set to infinity once, in stage 1, and kept across iterations)
+    persist = args.workload.startswith("persist-")
+    w = synth.WORKLOADS[args.workload.split("-", 1)[1] if persist else args.workload]
+    wl_name = ("persist-" if persist else "") + w.name
     dev = torch.device("cuda", 0)
     print(f"[bench] generating {w.name} {w.dims} on the GPU", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -369,7 +383,8 @@ def main():
            "counts": torch.empty(K, dtype=torch.int64, device=dev)}
 
     def step():
-        ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity, out=out, sync=False)
+        ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity, out=out, sync=False,
+                persist_distance=persist)
 
     for _ in range(args.warmup):
         step()
@@ -386,7 +401,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = {}
-    for k in ("seed", "bins", "sweep", "finalize", "connectivity"):
+    for k in ("seed", "bins", "sweep", "assign_persist", "update", "finalize", "connectivity"):
         ms = ctypes.c_double(0)
         n = ctypes.c_int64(0)
         sslic._check(L.sslic_profile_read(ctx._h, k.encode(), ctypes.byref(ms), ctypes.byref(n)))
@@ -401,22 +416,25 @@ def main():
     # adds labels K, K+1, ...)
     lab = out["labels"]
     n_labels = ctx.run(img, w.S, w.m, w.iterations, connectivity=w.connectivity,
-                       out=out)["n_labels"]
+                       out=out, persist_distance=persist)["n_labels"]
     assert int(lab.min()) >= 0 and int(lab.max()) < n_labels
 
     ms_step = dt / args.steps * 1e3
     value = N * w.iterations * args.steps / dt / 1e6
     # the iteration loop alone (bin sort, sweep, reduce step over every iteration)
-    loop_ms = sum(prof[k]["ms_total"] for k in ("bins", "sweep", "finalize") if k in prof) / args.steps
+    loop_ms = sum(prof[k]["ms_total"] for k in ("bins", "sweep", "assign_persist", "update", "finalize")
+                  if k in prof) / args.steps
     copy_gbs = copy_rate_gbs()
-    valu = load_profile("valu", "sweep", w.name)
+    valu = None if persist else load_profile("valu", "sweep", w.name)
     dt_name = {torch.uint8: "u8", torch.uint16: "u16", torch.float32: "f32"}[w.dtype]
-    # the sweep (assignment + map step) reads the image once and writes the labels once
-    per_vox = w.channels * BYTES[dt_name] + 4
-    dom = "sweep"
+    # the sweep (assignment + map step) reads the image once and writes the
+    # labels once; the kept-distance assignment reads the image and the
+    # distance and (at most) writes label and distance of every voxel
+    per_vox = w.channels * BYTES[dt_name] + (12 if persist else 4)
+    dom = "assign_persist" if persist else "sweep"
     bytes_launch = N * per_vox
     achieved = bytes_launch / (prof[dom]["ms_mean"] * 1e-3) / 1e9
-    traffic = load_traffic(dom, w.name)
+    traffic = load_traffic(dom, wl_name)
     # algorithmic FP32 work: every window covering a voxel costs one distance,
     # 3 flops per term (difference, multiply-add) over nd + C terms, with the
     # compare in place of the first term's add; windows cover K prod(2 S_i)
@@ -439,9 +457,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "dims": list(w.dims), "channels": w.channels,
+        "config": {"workload": wl_name, "dims": list(w.dims), "channels": w.channels,
                    "image_dtype": dt_name, "S": list(w.S), "m": w.m,
                    "iterations": w.iterations, "connectivity": w.connectivity, "K": K,
+                   "distance_image": "kept across iterations" if persist else "reset every iteration",
                    "recipe": w.recipe},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3),
                      "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
@@ -461,7 +480,7 @@ def main():
     }
     crop = args.cpu_crop if args.cpu_crop >= 0 else (4096 if len(w.dims) == 2 else 224)
     if crop > 0:
-        v, sec, desc = cpu_baseline(img, w, crop)
+        v, sec, desc = cpu_baseline(img, w, crop, persist)
         rec["cpu_baseline"] = {"value": round(v, 3), "unit": "Mvoxel*iter/s", "cores": 1,
                                "kind": "oracle", "sample": desc, "seconds": round(sec, 2)}
     print(json.dumps(rec), flush=True)

@@ -76,6 +76,15 @@ typedef struct {
                                  instead of replaying a captured HIP graph */
   int no_autotune;            /* sslic_run_batch: 1 = default tile shapes instead of
                                  the ones timed per (ndim, channels, dtype, S) */
+  int persist_distance;       /* sslic_run: 1 = the loop as Sec. 2.2 and Sec. 3.1
+                                 write it: the distance image is set to infinity once,
+                                 in stage 1, and kept across iterations (a voxel
+                                 changes label only where a centre comes strictly
+                                 closer than every earlier one); 0 = reset it at every
+                                 iteration, so that each assignment depends on the
+                                 current centres only (the default).  Adds 4 N bytes
+                                 of scratch; sslic_run_batch rejects it with
+                                 SSLIC_EUNSUPPORTED */
 } sslic_options;
 
 /* Create a context bound to HIP device `device_ordinal`.
@@ -106,6 +115,7 @@ int sslic_num_clusters(int ndim, const int64_t* dims, const int32_t* S, int64_t*
  *              wait for `stream`.
  * Scratch: the context's workspace grows to about
  *   K * (64 + 8 (channels + ndim + 1) (1 + 2^ndim)) + 4 ceil-bins + (connectivity ? 16 N : 0)
+ *   + (persist_distance ? 4 N : 0)
  * bytes and is reused across calls. */
 int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
               int channels, sslic_dtype dtype, const int32_t* S, double m, int iterations,

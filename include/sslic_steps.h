@@ -41,6 +41,22 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
                  int channels, sslic_dtype dtype, const int32_t* S, double m,
                  const double* centres, int64_t K, int32_t* labels, sslic_stream_t stream);
 
+/* One assignment step on a distance image the caller keeps between steps,
+ * the literal reading of the loops of Sec. 2.2 and Sec. 3.1 (there d is set to
+ * infinity once, in stage 1): for every voxel x, the least D^2(x, k) over
+ * the clusters whose closed window contains x (as in sslic_assign, FP32, ties
+ * to the smallest k) replaces dist[x], and its k replaces labels[x], only
+ * where it is strictly below dist[x]; elsewhere both are left as they are.
+ *   centres  device double [K][channels + ndim], read only
+ *   labels   device int32 [N], in/out
+ *   dist     device float [N], in/out: squared distances D^2 of Sec. 2.1 with
+ *            the spatial weight m^2 / S_i^2 per axis (Sec. 3.3); +inf where no
+ *            centre has reached yet.  Must not overlap image or labels. */
+int sslic_assign_persist(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
+                         int channels, sslic_dtype dtype, const int32_t* S, double m,
+                         const double* centres, int64_t K, int32_t* labels, float* dist,
+                         sslic_stream_t stream);
+
 /* One update step (Sec. 3.1 stage 2, map-reduce): every cluster with members
  * becomes the mean of [I(x), x] over the voxels labelled k; clusters without
  * members keep their row.  Integer images sum in int64 (bit-exact), float32

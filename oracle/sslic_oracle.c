@@ -26,8 +26,8 @@
  *   - window: closed, |x_i - c_i| <= S_i, evaluated as the integer range
  *     [ceil(c_i - S_i), floor(c_i + S_i)] (Sec. 2.2, Sec. 3.1);
  *   - the distance image is reset to +inf at the start of every iteration
- *     (or, with persist_distance, once before the first, as the original
- *     SLIC loop of Sec. 2.2 initialises it);
+ *     (or, with persist_distance, once before the first, as stage 1 of
+ *     Sec. 2.2 and Sec. 3.1 initialises it);
  *     voxels no window covers keep their previous label, and before the
  *     first iteration every voxel carries the label of its grid cell;
  *   - equal distances: the lower cluster index wins (strict "<" while
@@ -324,8 +324,8 @@ int or_assign(const void* img, int nd, const int64_t* dims, int C, int dtype,
 }
 
 /* The same step on a distance image the caller keeps between iterations, as
- * the original SLIC loop of Sec. 2.2 has it: d is set to infinity once,
- * before the first iteration, and a voxel changes label only where some
+ * the loops of Sec. 2.2 and Sec. 3.1 write it: d is set to infinity once, in
+ * stage 1, and a voxel changes label only where some
  * centre of this iteration comes strictly closer than the least distance it
  * has seen so far.
  *   dist  squared distances D^2 [N], read and updated in place */
@@ -657,8 +657,8 @@ int or_mask_contours(const void* img, int nd, const int64_t* dims, int C, int dt
 /* The whole filter: stage 1, the iterations of stage 2 and stage 3 (Sec. 3.1),
  * stopping early only when the residual drops below `tol` (Sec. 2.2
  * termination criterion; tol = 0 runs every iteration, as SSLIC does).  With
- * persist_distance the distance image lives across the iterations (Sec. 2.2
- * sets it to infinity once, before the loop). */
+ * persist_distance the distance image lives across the iterations (stage 1
+ * of Sec. 2.2 and Sec. 3.1 sets it to infinity once). */
 
 int or_run(const void* img, int nd, const int64_t* dims, int C, int dtype,
            const int32_t* S, double m, int iterations, double tol, int connectivity,

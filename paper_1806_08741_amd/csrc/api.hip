@@ -12,6 +12,7 @@
 
 #include "../../include/sslic_profile.h"
 #include "../../include/sslic_steps.h"
+#include "literal.h"
 #include "sslic_ctx.h"
 
 using namespace sslic;
@@ -86,7 +87,7 @@ int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, con
 
 size_t al(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
-Layout layout(const Geo& g, int iterations, bool cc, bool part) {
+Layout layout(const Geo& g, int iterations, bool cc, bool part, bool persist) {
   Layout L{};
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -112,6 +113,7 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part) {
     L.cc_part = put((size_t)cc_part_ints(g.N) * 4);
     L.cc_roots = put((size_t)g.N * 4);
   }
+  L.dist = put(persist ? (size_t)g.N * 4 : 0);
   L.total = o;
   return L;
 }
@@ -212,11 +214,15 @@ int read_ints(sslic_ctx* ctx, hipStream_t s, const int32_t* dev_a, int32_t* out_
 }
 
 // The iteration loop of one image on the context workspace.  Centres are in
-// `cen` (seeded or given) when called.
+// `cen` (seeded or given) when called.  With `dist` the loop keeps that
+// distance image across iterations (set to +inf once, here): each iteration
+// is then the persistent assignment step followed by the stand-alone update
+// (map step by atomics into acc, then the reduce step); otherwise the sweep
+// assigns and maps in one pass on a distance reset every iteration.
 int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* image, int iterations,
                    double tol, int32_t* labels, double* cen, int64_t* counts, double* residuals,
-                   hipStream_t s) {
-  const int slots = sweep_slots(g);
+                   float* dist, hipStream_t s) {
+  const int slots = dist ? 0 : sweep_slots(g);
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
   HIP_TRY(launch_fill_i32((int32_t*)it.accf, 0, (g.K + 3) / 4, s));
@@ -225,12 +231,23 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
   HIP_TRY(launch_prep(g, cen, it, s));
+  if (dist) {
+    HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(dist), 0x7f800000, g.N, s));  // +inf
+    HIP_TRY(launch_grid_labels(g, labels, s));  // what voxels no window reaches keep
+  }
   for (int t = 0; t < iterations; ++t) {
     {
       Mark mk(ctx, "bins", s);
       HIP_TRY(launch_bins(g, it, s));
     }
-    {
+    if (dist) {
+      {
+        Mark mk(ctx, "assign_persist", s);
+        HIP_TRY(launch_assign_persist(g, image, it, labels, dist, s));
+      }
+      Mark mk(ctx, "update", s);
+      HIP_TRY(launch_update(g, image, labels, it, s));
+    } else {
       Mark mk(ctx, "sweep", s);
       HIP_TRY(launch_sweep(g, image, it, labels, t, 1, s));
     }
@@ -308,7 +325,8 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
   const bool cc = !o.no_connectivity;
-  Layout L = layout(g, iterations, cc, true);
+  const bool persist = o.persist_distance != 0;
+  Layout L = layout(g, iterations, cc, !persist, persist);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Iter it = iter_view(ctx, L);
@@ -320,8 +338,9 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
     Mark mk(ctx, "seed", s);
     HIP_TRY(launch_seed(g, image, centres, s));
   }
+  float* dist = persist ? reinterpret_cast<float*>(ctx->ws + L.dist) : nullptr;
   if ((rc = run_iterations(ctx, g, it, image, iterations, o.tol, labels, centres, counts,
-                           o.residuals, s)))
+                           o.residuals, dist, s)))
     return rc;
   int32_t* nl = nlab_slot(ctx, L);
   if (cc) {
@@ -383,6 +402,33 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   HIP_TRY(launch_bins(g, it, s));
   // as a later iteration: voxels outside every window keep the given label
   HIP_TRY(launch_sweep(g, image, it, labels, 1, 0, s));
+  return SSLIC_OK;
+}
+
+int sslic_assign_persist(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
+                         int channels, sslic_dtype dtype, const int32_t* S, double m,
+                         const double* centres, int64_t K, int32_t* labels, float* dist,
+                         sslic_stream_t stream) {
+  if (!ctx || !image || !centres || !labels || !dist) return fail(SSLIC_EINVAL, "missing pointer");
+  if (K < 1) return fail(SSLIC_EINVAL, "K = %lld < 1", (long long)K);
+  Geo g;
+  int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, K);
+  if (rc) return rc;
+  const size_t nd4 = (size_t)g.N * 4;
+  const size_t ib = (size_t)g.N * channels * (dtype == kU8 ? 1 : dtype == kU16 ? 2 : 4);
+  const char *d = (const char*)dist, *a = (const char*)image, *l = (const char*)labels;
+  if (d < a + ib && a < d + nd4) return fail(SSLIC_EINVAL, "dist overlaps image");
+  if (d < l + nd4 && l < d + nd4) return fail(SSLIC_EINVAL, "dist overlaps labels");
+  if ((rc = select_device(ctx))) return rc;
+  Layout L = layout(g, 1, false, false);
+  if ((rc = ensure_ws(ctx, L.total))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Iter it = iter_view(ctx, L);
+  HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
+  HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
+  HIP_TRY(launch_prep(g, centres, it, s));
+  HIP_TRY(launch_bins(g, it, s));
+  HIP_TRY(launch_assign_persist(g, image, it, labels, dist, s));
   return SSLIC_OK;
 }
 

@@ -278,6 +278,8 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
   sslic_options o{};
   if (opt) o = *opt;
   if (!(o.tol >= 0.0)) return fail(SSLIC_EINVAL, "tol must be >= 0");
+  if (o.persist_distance)
+    return fail(SSLIC_EUNSUPPORTED, "persist_distance is a sslic_run option only");
   if (n == 0) return SSLIC_OK;
   int rc = SSLIC_OK;
 

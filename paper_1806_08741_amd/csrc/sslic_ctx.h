@@ -57,9 +57,10 @@ size_t al(size_t v);
 // sections of the single-image workspace
 struct Layout {
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part, acc, accf, part, res_acc, flags;
-  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, total;
+  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, dist, total;
 };
-Layout layout(const Geo& g, int iterations, bool cc, bool part);
+// persist: room for the distance image kept across iterations (f32 [N])
+Layout layout(const Geo& g, int iterations, bool cc, bool part, bool persist = false);
 int ensure_ws(sslic_ctx* ctx, size_t need);
 Iter iter_view(sslic_ctx* ctx, const Layout& L);
 CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N);

@@ -41,6 +41,7 @@ KERNELS = {
     "update": (r"update_kernel", ["update.hip", "sslic_internal.h"]),
     "contours": (r"mask_contours", ["contours.hip", "sslic_internal.h"]),
     "lab": (r"rgb_to_lab", ["lab.hip", "sslic_internal.h"]),
+    "assign_persist": (r"assign_persist_kernel", ["literal.hip", "literal.h", "sslic_internal.h"]),
 }
 
 

@@ -35,7 +35,8 @@ class SslicError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("tol", D), ("no_connectivity", I), ("init_centres", P), ("residuals", P),
-                ("iters_done_dev", P), ("n_labels_dev", P), ("no_graph", I), ("no_autotune", I)]
+                ("iters_done_dev", P), ("n_labels_dev", P), ("no_graph", I), ("no_autotune", I),
+                ("persist_distance", I)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -69,12 +70,14 @@ def lib():
             L.sslic_seed.argtypes = [P, P, I, P, I, I, P, P, P]
             L.sslic_grid_labels.argtypes = [P, I, P, P, P, P]
             L.sslic_assign.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P]
+            L.sslic_assign_persist.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P, P]
             L.sslic_update.argtypes = [P, P, I, P, I, I, P, D, P, I64, P, P, P, P]
             L.sslic_connectivity.argtypes = [P, I, P, P, I, P, I64, P, P, P, P]
             L.sslic_mask_contours.argtypes = [P, P, I, P, I, I, P, P, P]
             L.sslic_rgb_to_lab.argtypes = [P, P, I64, P, P]
             for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_batch",
-                         "sslic_seed", "sslic_grid_labels", "sslic_assign", "sslic_update",
+                         "sslic_seed", "sslic_grid_labels", "sslic_assign",
+                         "sslic_assign_persist", "sslic_update",
                          "sslic_connectivity", "sslic_mask_contours", "sslic_rgb_to_lab"):
                 getattr(L, name).restype = I
             _lib = L
@@ -148,10 +151,14 @@ class Context:
     def run(self, img: torch.Tensor, S: Sequence[int], m: float, iterations: int, *,
             tol: float = 0.0, connectivity: bool = True,
             init_centres: Optional[torch.Tensor] = None, residuals: bool = False,
-            out: Optional[dict] = None, sync: bool = True) -> dict:
+            out: Optional[dict] = None, sync: bool = True,
+            persist_distance: bool = False) -> dict:
         """Run SSLIC on one image.  ``out`` may hold preallocated ``labels``,
         ``centres``, ``counts`` tensors.  With ``sync`` the label count and the
-        iterations run are read back (the call then waits for the stream)."""
+        iterations run are read back (the call then waits for the stream).
+        ``persist_distance`` keeps the distance image across iterations (the
+        loop as Sec. 2.2 and Sec. 3.1 write it, d set to infinity once in
+        stage 1) instead of resetting it every iteration."""
         nd, dims, C, dt = _geom(img)
         K = num_clusters(dims, S)
         N = int(img.numel() // C)
@@ -167,7 +174,8 @@ class Context:
         if counts is None:
             counts = torch.empty(K, dtype=torch.int64, device=dev)
         res = torch.zeros(iterations, dtype=torch.float64, device=dev) if residuals else None
-        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None, 0, 0)
+        o = _Options(float(tol), 0 if connectivity else 1, None, None, None, None, 0, 0,
+                     1 if persist_distance else 0)
         if init_centres is not None:
             ic = init_centres.to(device=dev, dtype=torch.float64).contiguous()
             o.init_centres = ic.data_ptr()
@@ -278,6 +286,23 @@ class Context:
                                   _ptr(centres), centres.shape[0], _ptr(labels),
                                   _stream(img.device)))
         return labels
+
+    def assign_persist(self, img: torch.Tensor, S, m, centres: torch.Tensor,
+                       labels: torch.Tensor, dist: torch.Tensor):
+        """One assignment step on a kept distance image, in place on ``labels``
+        (int32) and ``dist`` (float32 squared distances, +inf where no centre
+        has reached yet)."""
+        nd, dims, C, dt = _geom(img)
+        centres = centres.to(device=img.device, dtype=torch.float64).contiguous()
+        for t, want in ((labels, torch.int32), (dist, torch.float32)):
+            if t.device != img.device or t.dtype != want or not t.is_contiguous():
+                raise SslicError(f"expected a contiguous {want} tensor on the image's device")
+            if t.numel() != img.numel() // C:
+                raise SslicError("labels and dist must hold one value per voxel")
+        _check(lib().sslic_assign_persist(self._h, _ptr(img), nd, _i64(dims), C, dt, _i32(S),
+                                          float(m), _ptr(centres), centres.shape[0],
+                                          _ptr(labels), _ptr(dist), _stream(img.device)))
+        return labels, dist
 
     def update(self, img: torch.Tensor, S, m, labels: torch.Tensor, centres: torch.Tensor):
         """One update step: returns (new centres, counts, residual tensor[1])."""

@@ -1,0 +1,186 @@
+"""GPU parity of the literal loop of Sec. 2.2 and Sec. 3.1, whose distance
+image is set to infinity once (stage 1) and kept across iterations (sslic_assign_persist and the
+persist_distance option of sslic_run), against the oracle on the same
+seeded inputs."""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1806_08741_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# One step from the same state: FP32 distances on the GPU against FP64 in
+# the oracle, so a voxel whose two best candidates (or whose best candidate
+# and its kept distance) differ by a rounding error may go either way.
+ASSIGN_TOL = 1e-4
+# Kept distances where the labels agree: FP32 D^2 in coordinates scaled by
+# m/S_i, at most ~1e3 here, so an absolute error of a few ulps of the scaled
+# coordinate times the difference (< 1e-2) on top of 1e-4 relative.
+DIST_RTOL, DIST_ATOL = 1e-4, 1e-2
+RUN_AGREE = 0.99
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1806_08741_amd import sslic
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return sslic.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rand_image(dims, C, dtype, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(dims[::-1]) + (C,)
+    if dtype == np.float32:
+        return rng.uniform(0, 255, size=shape).astype(np.float32)
+    top = {np.uint8: 255, np.uint16: 65535}[dtype]
+    return rng.integers(0, top + 1, size=shape).astype(dtype)
+
+
+CASES = [
+    ("rgb-256", (256, 256), (16, 16), 10.0),
+    ("slide-16k", (1000, 777), (16, 16), 10.0),
+    ("fibsem-1k", (90, 77, 65), (8, 8, 8), 20.0),
+    ("rand-u8-c5", (130, 70), (12, 9), 15.0),
+    ("rand-f32-c2", (67, 45, 19), (7, 6, 5), 5.0),
+    ("rand-u16-1d", (3001,), (16,), 10.0),
+    ("rand-u8-4d", (13, 11, 9, 7), (4, 4, 3, 3), 8.0),
+]
+
+
+def case_image(name, dims):
+    if name in synth.WORKLOADS:
+        return synth.workload_image(name, "cpu", dims=dims).numpy()
+    kind = name.split("-")
+    dt = {"u8": np.uint8, "u16": np.uint16, "f32": np.float32}[kind[1]]
+    C = int(kind[2][1:]) if kind[2].startswith("c") else (3 if dt == np.uint8 else 1)
+    return rand_image(dims, C, dt, sum(map(ord, name)))
+
+
+def oracle_state(img, nd, S, m, iters):
+    """Labels, kept distances and centres after `iters` oracle iterations of
+    the literal loop, stepped one function at a time."""
+    dims = img.shape[:nd][::-1]
+    cen = oracle.seed(img, nd, S)
+    lab = oracle.grid_labels(dims, S)
+    dist = np.full(lab.size, np.inf)
+    for _ in range(iters):
+        oracle.assign_persist(img, nd, S, m, cen, lab, dist)
+        cen, _, _ = oracle.update(img, nd, S, m, lab, cen)
+    return lab, dist, cen
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_assign_persist_one_step(ctx, name, dims, S, m):
+    img = case_image(name, dims)
+    nd = len(dims)
+    for iters in (0, 1, 3):
+        lab, dist, cen = oracle_state(img, nd, S, m, iters)
+        cen = cen.astype(np.float32).astype(np.float64)  # both sides see the same windows
+        exp_l, exp_d = oracle.assign_persist(img, nd, S, m, cen, lab.copy(), dist.copy())
+        gl, gd = dev(lab), dev(dist.astype(np.float32))
+        ctx.assign_persist(dev(img), S, m, dev(cen), gl, gd)
+        got_l, got_d = host(gl), host(gd)
+        frac = float((got_l != exp_l).mean())
+        assert frac <= ASSIGN_TOL, f"{name} after {iters}: {frac:.2e} of labels differ"
+        same = got_l == exp_l
+        np.testing.assert_allclose(got_d[same], exp_d[same], rtol=DIST_RTOL, atol=DIST_ATOL)
+        # the step changed something, and kept something, in every later state
+        if iters > 0:
+            assert (got_l != lab).any() or (got_d < dist.astype(np.float32)).any()
+            assert (got_d == dist.astype(np.float32)).any()
+
+
+@pytest.mark.parametrize("name,dims,S,m", CASES)
+def test_persist_run_matches_oracle(ctx, name, dims, S, m):
+    img = case_image(name, dims)
+    nd = len(dims)
+    K = int(np.prod([max(1, (2 * n + s) // (2 * s)) for n, s in zip(dims, S)]))
+    exp = oracle.run(img, nd, S, m, 5, connectivity=False, persist_distance=True)
+    got = ctx.run(dev(img), S, m, 5, connectivity=False, persist_distance=True)
+    gl = host(got["labels"])
+    assert gl.min() >= 0 and gl.max() < K
+    agree = float((gl == exp["labels"]).mean())
+    assert agree >= RUN_AGREE, f"{name}: {agree:.4f} agreement"
+    assert got["iterations"] == 5
+
+
+def test_persist_golden_1d(ctx):
+    """The hand-derived case where the kept distance and the reset differ."""
+    with open(os.path.join(GOLDEN, "persist_1d.json")) as fh:
+        gd = json.load(fh)
+    img = np.array(gd["image"], dtype=np.uint8).reshape(-1, 1)
+    init = torch.tensor(gd["init_centres"], dtype=torch.float64)
+    for mode, persist in (("reset", False), ("persist", True)):
+        r = ctx.run(dev(img), gd["S"], gd["m"], gd["iterations"], connectivity=False,
+                    init_centres=init, persist_distance=persist, residuals=True)
+        exp = oracle.run(img, 1, gd["S"], gd["m"], gd["iterations"], connectivity=False,
+                         init_centres=init.numpy(), persist_distance=persist)
+        np.testing.assert_array_equal(host(r["labels"]), gd[mode]["labels"])
+        np.testing.assert_array_equal(host(r["centres"]), exp["centres"])
+        if persist:
+            assert host(r["residuals"])[1] == 0.0
+
+
+def test_persist_equals_reset_on_cell_images(ctx):
+    """A checkerboard of S-cells (neighbouring cells 150+ apart, cells of one
+    colour a few units apart): every voxel's nearest centre is its own cell's
+    under either reading, so both runs give the cells, and the centres equal
+    the oracle's (integer sums, one FP64 division)."""
+    dims, S = (200, 136), (8, 8)
+    K, Ka = oracle.num_clusters(dims, S)
+    k = np.arange(K)
+    vals = 40 + 170 * ((k % Ka[0] + k // Ka[0]) % 2) + 3 * (k % 7)
+    cell = oracle.grid_labels(dims, S)
+    img = np.repeat(vals[cell].astype(np.uint8).reshape(dims[::-1] + (1,)), 3, axis=-1)
+    a = ctx.run(dev(img), S, 10.0, 6, connectivity=False)
+    b = ctx.run(dev(img), S, 10.0, 6, connectivity=False, persist_distance=True)
+    exp = oracle.run(img, 2, S, 10.0, 6, connectivity=False, persist_distance=True)
+    np.testing.assert_array_equal(exp["labels"], cell)
+    np.testing.assert_array_equal(host(b["labels"]), cell)
+    np.testing.assert_array_equal(host(a["labels"]), cell)
+    np.testing.assert_array_equal(host(b["centres"]), exp["centres"])
+
+
+def test_persist_with_connectivity_and_after_other_runs(ctx):
+    """The option leaves the other paths of the same context as they were."""
+    img = case_image("rgb-256", (256, 256))
+    before = host(ctx.run(dev(img), (16, 16), 10.0, 4)["labels"])
+    p = ctx.run(dev(img), (16, 16), 10.0, 4, persist_distance=True)
+    exp = oracle.run(img, 2, (16, 16), 10.0, 4, persist_distance=True)
+    agree = float((host(p["labels"]) == exp["labels"]).mean())
+    assert agree >= RUN_AGREE
+    after = host(ctx.run(dev(img), (16, 16), 10.0, 4)["labels"])
+    np.testing.assert_array_equal(after, before)
+
+
+def test_persist_rejections(ctx):
+    from paper_1806_08741_amd import sslic
+    img = dev(case_image("rgb-256", (256, 256)))
+    cen = torch.from_numpy(oracle.seed(case_image("rgb-256", (256, 256)), 2, (16, 16))).cuda()
+    lab = torch.zeros(256 * 256, dtype=torch.int32, device="cuda")
+    with pytest.raises(sslic.SslicError):
+        ctx.assign_persist(img, (16, 16), 10.0, cen, lab, lab.view(torch.float32))
+    with pytest.raises(sslic.SslicError):
+        ctx.assign_persist(img, (16, 16), 10.0, cen, lab,
+                           torch.zeros(100, dtype=torch.float32, device="cuda"))
+    o = sslic._Options(0.0, 1, None, None, None, None, 0, 0, 1)
+    rc = sslic.lib().sslic_run_batch(ctx._h, None, 0, ctypes.byref(o), None, None)
+    assert rc == -4  # SSLIC_EUNSUPPORTED

@@ -1,7 +1,7 @@
 """Pins of the oracle's functions beyond the SLIC path proper: the contour
 mask of the paper's visualisation (Sec. 4), checked against closed forms of
 hand-built label images on 1 to 4 axes; the RGB to CIE-Lab conversion; and
-the assignment on a distance image kept across iterations (Sec. 2.2).  CPU
+the assignment on a distance image kept across iterations (Sec. 2.2, Sec. 3.1).  CPU
 only."""
 import json
 import os
@@ -122,7 +122,7 @@ def test_lab_of_pure_red():
     np.testing.assert_allclose(lab, [53.24, 80.09, 67.20], atol=0.05)
 
 
-# ---- distance image kept across iterations (Sec. 2.2) ----------------------
+# ---- distance image kept across iterations (Sec. 2.2, Sec. 3.1) ------------
 
 def test_persist_golden_1d_separates_the_two_readings():
     with open(os.path.join(GOLDEN, "persist_1d.json")) as fh:
