@@ -5,15 +5,17 @@
 // is a voxel-parallel gather whose labels the stand-alone update step then
 // sums.
 //
-// One thread per voxel.  A workgroup takes 64 consecutive voxels along axis 0
-// on 4 x kRowsPerWave rows (the other axes flattened); each wave walks
-// kRowsPerWave rows.  Every centre whose closed window holds x lies in the
-// 3^n bins around floor(x_i / S_i) (a centre's bin is the S-cell of its
-// window's low corner, plus one); along axis 0 those bins are one contiguous
-// range of the bin-ordered item list, so a voxel reads 3^(n-1) ranges.  The
-// lanes of a wave share almost all of their ranges, so the records come from
-// the caches.  Distances are FP32 in the scaled coordinates of the records,
-// the same terms in the same order as the sweep.
+// A wave takes one block of 64 voxels (8x8 in 2D, 4x4x4 in 3D, 4x4x2x2 in
+// 4D), one voxel per lane.  Every centre whose closed window holds a voxel of
+// the block is in the bins within one bin of the block (a centre's bin is the
+// S-cell of its window's low corner, plus one).  The wave first gathers those
+// centres, lane j the j-th, with their records (all loads in flight at
+// once), and ballots which windows meet the block; it then walks the meeting
+// ones, broadcasting each record from its lane, while every lane tests its own
+// voxel and evaluates the FP32 distance in the scaled coordinates of the
+// records (the same terms in the same order as the sweep).  The least
+// (D^2, k) is one 64-bit key.  A block with more than 64 such centres walks
+// them one by one with scalar loads instead.
 #include "literal.h"
 
 namespace sslic {
@@ -21,86 +23,155 @@ namespace sslic {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsPerWave = 4;
-constexpr int kRowsPerBlock = kRowsPerWave * (kThreads / 64);
+constexpr int kWaves = kThreads / 64;
+
+template <int ND>
+struct Blk;
+template <>
+struct Blk<2> {
+  static constexpr int B[2] = {8, 8};
+};
+template <>
+struct Blk<3> {
+  static constexpr int B[3] = {4, 4, 4};
+};
+template <>
+struct Blk<4> {
+  static constexpr int B[4] = {4, 4, 2, 2};
+};
 
 template <typename T, int ND, int CC>
 __global__ void __launch_bounds__(kThreads)
-assign_persist_kernel(Geo g, const T* __restrict__ img, Iter it, int32_t* __restrict__ labels,
-                      float* __restrict__ dist, int64_t nrows) {
-  if (*it.done) return;
+assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict__ recs,
+                      const int* __restrict__ bstart, const int* __restrict__ items,
+                      const int* __restrict__ done, int32_t* __restrict__ labels,
+                      float* __restrict__ dist, int64_t nblocks) {
+  if (*done) return;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
+  constexpr int RN = (CM + 3 * ND + 1 + 3) & ~3;  // record words (rec_words)
   const int C = CC > 0 ? CC : g.C;
   const int RS = g.rs;
-  const float* __restrict__ recs = it.ctab;
-  const int* __restrict__ irecs = reinterpret_cast<const int*>(it.ctab);
-  const int* __restrict__ bstart = it.bin_start;
-  const int* __restrict__ items = it.bin_items;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  if (b >= nblocks) return;  // no barrier in this kernel
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n0 = g.n[0];
-  const int64_t tiles_x = (n0 + 63) / 64;
-  const int x0 = (int)(blockIdx.x % tiles_x) * 64 + lane;
-  if (x0 >= n0) return;  // no barrier below
-  const int64_t rbase = (int64_t)(blockIdx.x / tiles_x) * kRowsPerBlock + wave * kRowsPerWave;
+  // the block (axis 0 fastest over blocks) and this lane's voxel in it
+  int org[ND], top[ND], x[ND];
+  int64_t rb = b;
+  int lr = lane;
+  bool valid = true;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    const int Bi = Blk<ND>::B[i];
+    const int nbi = (g.n[i] + Bi - 1) / Bi;
+    org[i] = (int)(rb % nbi) * Bi;
+    rb /= nbi;
+    top[i] = min(org[i] + Bi, g.n[i]) - 1;
+    x[i] = org[i] + lr % Bi;
+    lr /= Bi;
+    valid = valid && x[i] <= top[i];
+  }
+  int64_t v = 0;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) v += (int64_t)(valid ? x[i] : org[i]) * g.st[i];
+  float xs[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) xs[i] = (float)x[i] * g.sw[i];
+  float I[CM];
+  for (int c = 0; c < C; ++c) I[c] = (float)img[v * C + c];
 
-  const int b0 = x0 / g.S[0];
-  const int lo0 = max(b0 - 1, 0), hi0 = min(b0 + 1, g.nb[0] - 1);
-  const float xs0 = (float)x0 * g.sw[0];
-
-  for (int j = 0; j < kRowsPerWave; ++j) {
-    const int64_t r = rbase + j;
-    if (r >= nrows) break;
-    int x[ND];
-    float xs[ND];
-    int blo[ND], bhi[ND];
-    x[0] = x0;
-    xs[0] = xs0;
-    int64_t rr = r;
-    for (int i = 1; i < ND; ++i) {
-      x[i] = (int)(rr % g.n[i]);
-      rr /= g.n[i];
-      xs[i] = (float)x[i] * g.sw[i];
-      const int b = x[i] / g.S[i];
-      blo[i] = max(b - 1, 0);
-      bhi[i] = min(b + 1, g.nb[i] - 1);
+  int blo[ND], bhi[ND], rc[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    blo[i] = max(org[i] / g.S[i] - 1, 0);
+    bhi[i] = min(top[i] / g.S[i] + 1, g.nb[i] - 1);
+    rc[i] = blo[i];
+  }
+  uint64_t best = ~0ull;
+  auto consider = [&](const float* R, uint32_t k) {
+    const int* Ri = reinterpret_cast<const int*>(R);
+    bool in = valid;
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+      in = in && x[i] >= Ri[rec_lo(C, ND) + i] && x[i] <= Ri[rec_hi(C, ND) + i];
+    float D;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const float d = xs[i] - R[C + i];
+      D = i == 0 ? d * d : fmaf(d, d, D);
     }
-    const int64_t v = r * n0 + x0;
-    float I[CM];
-    for (int c = 0; c < C; ++c) I[c] = (float)img[v * C + c];
+    for (int c = 0; c < C; ++c) {
+      const float t = I[c] - R[c];
+      D = fmaf(t, t, D);
+    }
+    const uint64_t key = (uint64_t)__float_as_uint(D) << 32 | k;
+    if (in && key < best) best = key;
+  };
 
-    float best = __builtin_inff();
-    int bk = -1;
-    int rc[ND];
-    for (int i = 1; i < ND; ++i) rc[i] = blo[i];
+  // Gather: lane j takes the j-th centre of the bin rows around the block, and
+  // its record, with every load of the wave in flight at once.
+  int myk = 0, cnt = 0;
+  while (true) {
+    int64_t bl = (int64_t)blo[0] * g.bst[0];
+#pragma unroll
+    for (int i = 1; i < ND; ++i) bl += (int64_t)rc[i] * g.bst[i];
+    const int ja = __builtin_amdgcn_readfirstlane(bstart[bl]);
+    const int jb = __builtin_amdgcn_readfirstlane(bstart[bl + (bhi[0] - blo[0]) + 1]);
+    const int j = lane - cnt;
+    if (j >= 0 && j < jb - ja) myk = items[ja + j];
+    cnt += jb - ja;
+    int i = 1;
+    while (i < ND) {
+      if (++rc[i] <= bhi[i]) break;
+      rc[i] = blo[i];
+      ++i;
+    }
+    if (i >= ND) break;
+  }
+  if (cnt <= 64) {
+    const bool held = lane < cnt;
+    const float* rec = recs + (int64_t)(held ? myk : 0) * RS;
+    float MR[RN];
+#pragma unroll
+    for (int w = 0; w < RN; ++w) MR[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+    const int* MRi = reinterpret_cast<const int*>(MR);
+    bool meets = held;
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+      meets = meets && MRi[rec_lo(C, ND) + i] <= top[i] && MRi[rec_hi(C, ND) + i] >= org[i];
+    uint64_t mask = __ballot(meets);
+    while (mask) {
+      const int l = (int)__builtin_ctzll(mask);
+      mask &= mask - 1;
+      float R[RN];
+#pragma unroll
+      for (int w = 0; w < RN; ++w)
+        R[w] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(MR[w]), l));
+      consider(R, (uint32_t)__builtin_amdgcn_readlane(myk, l));
+    }
+  } else {
+    // more centres than lanes (a crowded neighbourhood): walk them one by one
+#pragma unroll
+    for (int i = 0; i < ND; ++i) rc[i] = blo[i];
     while (true) {
-      int64_t bl = (int64_t)lo0 * g.bst[0];
+      int64_t bl = (int64_t)blo[0] * g.bst[0];
+#pragma unroll
       for (int i = 1; i < ND; ++i) bl += (int64_t)rc[i] * g.bst[i];
-      const int ja = bstart[bl];
-      const int jb = bstart[bl + (hi0 - lo0) + 1];
+      const int ja = __builtin_amdgcn_readfirstlane(bstart[bl]);
+      const int jb = __builtin_amdgcn_readfirstlane(bstart[bl + (bhi[0] - blo[0]) + 1]);
       for (int q = ja; q < jb; ++q) {
-        const int k = items[q];
-        const int* ir = irecs + (int64_t)k * RS;
-        bool ok = true;
+        const int k = __builtin_amdgcn_readfirstlane(items[q]);
+        const float* rec = recs + (int64_t)k * RS;
+        float R[RN];
+#pragma unroll
+        for (int w = 0; w < RN; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
+        const int* Ri = reinterpret_cast<const int*>(R);
+        bool meets = true;
 #pragma unroll
         for (int i = 0; i < ND; ++i)
-          ok = ok && x[i] >= ir[rec_lo(C, ND) + i] && x[i] <= ir[rec_hi(C, ND) + i];
-        if (!ok) continue;
-        const float* rec = recs + (int64_t)k * RS;
-        float D = 0.0f;
-#pragma unroll
-        for (int i = 0; i < ND; ++i) {
-          const float d = xs[i] - rec[C + i];
-          D = i == 0 ? d * d : fmaf(d, d, D);
-        }
-        for (int c = 0; c < C; ++c) {
-          const float t = I[c] - rec[c];
-          D = fmaf(t, t, D);
-        }
-        if (D < best || (D == best && k < bk)) {
-          best = D;
-          bk = k;
-        }
+          meets = meets && Ri[rec_lo(C, ND) + i] <= top[i] && Ri[rec_hi(C, ND) + i] >= org[i];
+        if (meets) consider(R, (uint32_t)k);
       }
       int i = 1;
       while (i < ND) {
@@ -110,9 +181,12 @@ assign_persist_kernel(Geo g, const T* __restrict__ img, Iter it, int32_t* __rest
       }
       if (i >= ND) break;
     }
-    if (bk >= 0 && best < dist[v]) {
-      labels[v] = bk;
-      dist[v] = best;
+  }
+  if (valid && best != ~0ull) {
+    const float D = __uint_as_float((uint32_t)(best >> 32));
+    if (D < dist[v]) {
+      labels[v] = (int32_t)(uint32_t)best;
+      dist[v] = D;
     }
   }
 }
@@ -120,18 +194,20 @@ assign_persist_kernel(Geo g, const T* __restrict__ img, Iter it, int32_t* __rest
 template <typename T, int ND>
 hipError_t dispatch_c(const Geo& g, const void* img, const Iter& it, int32_t* labels, float* dist,
                       hipStream_t s) {
-  const int64_t tiles_x = (g.n[0] + 63) / 64;
-  const int64_t nrows = g.N / g.n[0];
-  const int64_t nb = tiles_x * ((nrows + kRowsPerBlock - 1) / kRowsPerBlock);
-  if (nb <= 0) return hipSuccess;
-  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  int64_t nblocks = 1;
+  for (int i = 0; i < ND; ++i) nblocks *= (g.n[i] + Blk<ND>::B[i] - 1) / Blk<ND>::B[i];
+  const int64_t nwg = (nblocks + kWaves - 1) / kWaves;
+  if (nwg <= 0) return hipSuccess;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   const T* p = (const T*)img;
-  const unsigned grid = (unsigned)nb;
+  const unsigned grid = (unsigned)nwg;
+  const float* r = it.ctab;
+  const int *bs = it.bin_start, *items = it.bin_items, *done = it.done;
   switch (g.C) {
-    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, it, labels, dist, nrows); break;
-    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, it, labels, dist, nrows); break;
-    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, it, labels, dist, nrows); break;
-    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, it, labels, dist, nrows); break;
+    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
+    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
+    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
+    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
   }
   return hipGetLastError();
 }
