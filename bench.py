@@ -288,6 +288,20 @@ def bench_contours(args, base: str):
                      "algorithmic_bytes_per_launch": N * per_vox,
                      "hbm_achievable_copy": round(copy_rate_gbs(), 1)},
     }
+    # the oracle, one thread, on the leading crop of image and labels
+    import oracle
+    nd = len(w.dims)
+    side = 16384 if nd == 2 else 512
+    sl = tuple(slice(0, min(side, d)) for d in reversed(w.dims))
+    sub = img[sl].contiguous().cpu().numpy()
+    sub_lab = lab.view(*reversed(w.dims))[sl].contiguous().cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.mask_contours(sub, nd, sub_lab)
+    sec = time.perf_counter() - t0
+    vox = int(np.prod(sub_lab.shape))
+    rec["cpu_baseline"] = {"value": round(vox / sec / 1e9, 4), "unit": "Gvoxel/s", "cores": 1,
+                           "kind": "oracle", "seconds": round(sec, 2),
+                           "sample": "leading " + "x".join(str(min(side, d)) for d in w.dims) + " crop"}
     print(json.dumps(rec), flush=True)
 
 
@@ -328,6 +342,15 @@ def bench_lab(args):
                      "algorithmic_bytes_per_launch": N * 15,
                      "hbm_achievable_copy": round(copy_rate_gbs(), 1)},
     }
+    # the oracle, one thread, on the leading 4096x4096 crop
+    import oracle
+    sub = img[:4096, :4096].contiguous().cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.rgb_to_lab(sub)
+    sec = time.perf_counter() - t0
+    rec["cpu_baseline"] = {"value": round(sub.shape[0] * sub.shape[1] / sec / 1e9, 4),
+                           "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+                           "seconds": round(sec, 2), "sample": "leading 4096x4096 crop"}
     print(json.dumps(rec), flush=True)
 
 

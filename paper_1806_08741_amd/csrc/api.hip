@@ -231,10 +231,8 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   if (residuals) HIP_TRY(launch_fill_f64(residuals, 0.0, iterations, s));
   HIP_TRY(launch_prep(g, cen, it, s));
-  if (dist) {
-    HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(dist), 0x7f800000, g.N, s));  // +inf
-    HIP_TRY(launch_grid_labels(g, labels, s));  // what voxels no window reaches keep
-  }
+  // +inf; the first assignment writes the grid cell where no window reaches
+  if (dist) HIP_TRY(launch_fill_i32(reinterpret_cast<int32_t*>(dist), 0x7f800000, g.N, s));
   for (int t = 0; t < iterations; ++t) {
     {
       Mark mk(ctx, "bins", s);
@@ -243,7 +241,7 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
     if (dist) {
       {
         Mark mk(ctx, "assign_persist", s);
-        HIP_TRY(launch_assign_persist(g, image, it, labels, dist, s));
+        HIP_TRY(launch_assign_persist(g, image, it, labels, dist, t == 0, s));
       }
       Mark mk(ctx, "update", s);
       HIP_TRY(launch_update(g, image, labels, it, s));
@@ -428,7 +426,7 @@ int sslic_assign_persist(sslic_ctx* ctx, const void* image, int ndim, const int6
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_prep(g, centres, it, s));
   HIP_TRY(launch_bins(g, it, s));
-  HIP_TRY(launch_assign_persist(g, image, it, labels, dist, s));
+  HIP_TRY(launch_assign_persist(g, image, it, labels, dist, 0, s));
   return SSLIC_OK;
 }
 

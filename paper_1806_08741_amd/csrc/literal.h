@@ -10,10 +10,12 @@ namespace sslic {
 // centre has reached yet): for every voxel x, the least D^2 over the centres
 // of `it` whose closed window holds x, ties to the smaller k; where it is
 // strictly below dist[x], labels[x] and dist[x] take the centre and its D^2.
-// Elsewhere both are left as they are.  Needs the records and the bin index
-// of the centres (launch_prep, launch_bins).  Returns at once when the
-// iteration loop's stop flag is set.
+// Elsewhere both are left as they are, except that with `first` a voxel no
+// window holds gets the label of its grid cell (the starting labels of the
+// run, written here instead of in a pass of their own).  Needs the records
+// and the bin index of the centres (launch_prep, launch_bins).  Returns at
+// once when the iteration loop's stop flag is set.
 hipError_t launch_assign_persist(const Geo& g, const void* img, const Iter& it, int32_t* labels,
-                                 float* dist, hipStream_t s);
+                                 float* dist, int first, hipStream_t s);
 
 }  // namespace sslic

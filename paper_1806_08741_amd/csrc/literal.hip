@@ -40,12 +40,28 @@ struct Blk<4> {
   static constexpr int B[4] = {4, 4, 2, 2};
 };
 
+// Grid cell of voxel x: sum_i floor(x_i K_i / N_i) prod_{i'<i} K_i'.
+template <int ND>
+__device__ __forceinline__ int32_t cell_of(const Geo& g, const int* x) {
+  int64_t k = 0, kst = 1;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    k += ((int64_t)x[i] * g.Ka[i] / g.n[i]) * kst;
+    kst *= g.Ka[i];
+  }
+  return (int32_t)k;
+}
+
+// Workgroup w of a grid of G (a multiple of 8) takes the blocks of tile
+// (w mod 8) * (G / 8) + w div 8: workgroups go round the 8 XCDs in turn, so
+// neighbouring tiles, whose image and distance lines overlap, run on one XCD
+// and share its L2.
 template <typename T, int ND, int CC>
 __global__ void __launch_bounds__(kThreads)
 assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict__ recs,
                       const int* __restrict__ bstart, const int* __restrict__ items,
                       const int* __restrict__ done, int32_t* __restrict__ labels,
-                      float* __restrict__ dist, int64_t nblocks) {
+                      float* __restrict__ dist, int64_t nblocks, int first) {
   if (*done) return;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   constexpr int RN = (CM + 3 * ND + 1 + 3) & ~3;  // record words (rec_words)
@@ -53,7 +69,8 @@ assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict_
   const int RS = g.rs;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t b = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t b = tile * kWaves + wave;
   if (b >= nblocks) return;  // no barrier in this kernel
 
   // the block (axis 0 fastest over blocks) and this lane's voxel in it
@@ -187,16 +204,20 @@ assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict_
     if (D < dist[v]) {
       labels[v] = (int32_t)(uint32_t)best;
       dist[v] = D;
+    } else if (first) {
+      labels[v] = cell_of<ND>(g, x);
     }
+  } else if (valid && first) {
+    labels[v] = cell_of<ND>(g, x);
   }
 }
 
 template <typename T, int ND>
 hipError_t dispatch_c(const Geo& g, const void* img, const Iter& it, int32_t* labels, float* dist,
-                      hipStream_t s) {
+                      int first, hipStream_t s) {
   int64_t nblocks = 1;
   for (int i = 0; i < ND; ++i) nblocks *= (g.n[i] + Blk<ND>::B[i] - 1) / Blk<ND>::B[i];
-  const int64_t nwg = (nblocks + kWaves - 1) / kWaves;
+  const int64_t nwg = ((nblocks + kWaves - 1) / kWaves + 7) / 8 * 8;  // whole rounds of 8 XCDs
   if (nwg <= 0) return hipSuccess;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   const T* p = (const T*)img;
@@ -204,32 +225,32 @@ hipError_t dispatch_c(const Geo& g, const void* img, const Iter& it, int32_t* la
   const float* r = it.ctab;
   const int *bs = it.bin_start, *items = it.bin_items, *done = it.done;
   switch (g.C) {
-    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
-    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
-    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
-    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks); break;
+    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
+    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
+    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
+    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
   }
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t dispatch_nd(const Geo& g, const void* img, const Iter& it, int32_t* labels, float* dist,
-                       hipStream_t s) {
+                       int first, hipStream_t s) {
   switch (g.nd) {
-    case 2: return dispatch_c<T, 2>(g, img, it, labels, dist, s);
-    case 3: return dispatch_c<T, 3>(g, img, it, labels, dist, s);
-    default: return dispatch_c<T, 4>(g, img, it, labels, dist, s);
+    case 2: return dispatch_c<T, 2>(g, img, it, labels, dist, first, s);
+    case 3: return dispatch_c<T, 3>(g, img, it, labels, dist, first, s);
+    default: return dispatch_c<T, 4>(g, img, it, labels, dist, first, s);
   }
 }
 
 }  // namespace
 
 hipError_t launch_assign_persist(const Geo& g, const void* img, const Iter& it, int32_t* labels,
-                                 float* dist, hipStream_t s) {
+                                 float* dist, int first, hipStream_t s) {
   switch (g.dtype) {
-    case kU8: return dispatch_nd<uint8_t>(g, img, it, labels, dist, s);
-    case kU16: return dispatch_nd<uint16_t>(g, img, it, labels, dist, s);
-    default: return dispatch_nd<float>(g, img, it, labels, dist, s);
+    case kU8: return dispatch_nd<uint8_t>(g, img, it, labels, dist, first, s);
+    case kU16: return dispatch_nd<uint16_t>(g, img, it, labels, dist, first, s);
+    default: return dispatch_nd<float>(g, img, it, labels, dist, first, s);
   }
 }
 

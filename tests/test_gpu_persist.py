@@ -184,3 +184,33 @@ def test_persist_rejections(ctx):
     o = sslic._Options(0.0, 1, None, None, None, None, 0, 0, 1)
     rc = sslic.lib().sslic_run_batch(ctx._h, None, 0, ctypes.byref(o), None, None)
     assert rc == -4  # SSLIC_EUNSUPPORTED
+
+
+def test_persist_run_uncovered_voxels_keep_grid_cells(ctx):
+    """Centres of a 4x4 block of cells moved to the far corner leave voxels no
+    window reaches in the first iteration: they keep their grid cell.  With
+    m = S the scaled coordinates are the integer ones, so every distance of
+    the first iteration is exact in FP32 and the labels match exactly."""
+    rng = np.random.default_rng(9)
+    dims, S, m = (64, 48), (4, 4), 4.0
+    img = rand_image(dims, 1, np.uint8, 3)
+    K, Ka = oracle.num_clusters(dims, S)
+    grid = np.stack(np.meshgrid(*[np.arange(k) * 4 + 2.0 for k in Ka], indexing="ij"), -1)
+    init = np.zeros((K, 3))
+    init[:, 1:] = grid.reshape(-1, 2, order="F")
+    init[:, 0] = rng.integers(0, 256, K)
+    for jy in range(3, 7):
+        for jx in range(3, 7):
+            init[jx + Ka[0] * jy, 1:] = (62.0, 46.0)
+    cell = oracle.grid_labels(dims, S)
+    for T in (1, 3):
+        exp = oracle.run(img, 2, S, m, T, connectivity=False, init_centres=init,
+                         persist_distance=True)
+        got = host(ctx.run(dev(img), S, m, T, connectivity=False,
+                           init_centres=torch.from_numpy(init), persist_distance=True)["labels"])
+        if T == 1:
+            kept = exp["labels"] == cell
+            assert kept.sum() > 50  # uncovered voxels really are there
+            np.testing.assert_array_equal(got, exp["labels"])
+        else:
+            assert float((got == exp["labels"]).mean()) >= RUN_AGREE
