@@ -214,3 +214,34 @@ def test_persist_run_uncovered_voxels_keep_grid_cells(ctx):
             np.testing.assert_array_equal(got, exp["labels"])
         else:
             assert float((got == exp["labels"]).mean()) >= RUN_AGREE
+
+
+def _checkerboard(dims, S):
+    K, Ka = oracle.num_clusters(dims, S)
+    k = np.arange(K)
+    vals = 40 + 170 * ((k % Ka[0] + k // Ka[0]) % 2) + 3 * (k % 7)
+    cell = oracle.grid_labels(dims, S)
+    return np.repeat(vals[cell].astype(np.uint8).reshape(dims[::-1] + (1,)), 3, axis=-1)
+
+
+def test_persist_tol_stops_on_device(ctx):
+    img = _checkerboard((96, 64), (8, 8))
+    got = ctx.run(dev(img), (8, 8), 10.0, 10, connectivity=False, tol=1e-9, residuals=True,
+                  persist_distance=True)
+    exp = oracle.run(img, 2, (8, 8), 10.0, 10, connectivity=False, tol=1e-9,
+                     persist_distance=True)
+    assert got["iterations"] == exp["iterations"] < 10
+    np.testing.assert_array_equal(host(got["labels"]), exp["labels"])
+    np.testing.assert_allclose(host(got["residuals"]), exp["residuals"], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("dims,S", [((1,), (1,)), ((1, 1), (1, 1)), ((1, 1, 1), (1, 1, 1)),
+                                    ((3, 1), (5, 5)), ((2, 2, 2, 2), (1, 1, 1, 1))])
+def test_persist_degenerate_sizes(ctx, dims, S):
+    img = rand_image(dims, 3, np.uint8, 4)
+    nd = len(dims)
+    exp = oracle.run(img, nd, S, 10.0, 3, persist_distance=True)
+    got = ctx.run(dev(img), S, 10.0, 3, persist_distance=True)
+    np.testing.assert_array_equal(host(got["labels"]), exp["labels"])
+    np.testing.assert_array_equal(host(got["centres"]), exp["centres"])
+    assert got["n_labels"] == exp["n_labels"]
