@@ -52,7 +52,12 @@ CASES = [((300, 211), (16, 16), 3, np.uint8), ((700, 3), (8, 2), 1, np.uint16),
          ((9, 8, 7, 6), (3, 3, 3, 2), 4, np.uint8), ((257, 130), (12, 12), 5, np.uint16),
          # widths whose rows suit the four-voxel vector path
          ((64, 30, 17), (8, 8, 8), 1, np.uint16), ((32, 20), (4, 4), 4, np.float32),
-         ((1024, 9), (16, 3), 3, np.uint8)]
+         ((1024, 9), (16, 3), 3, np.uint8),
+         # 3D widths for the plane-walking path: several and ragged z-chunks,
+         # every channel count it takes, two x-segments
+         ((32, 10, 70), (4, 4, 4), 1, np.uint8), ((48, 7, 40), (6, 6, 6), 3, np.uint8),
+         ((12, 5, 66), (3, 3, 3), 4, np.float32), ((1032, 3, 35), (8, 2, 8), 1, np.uint16),
+         ((16, 16, 33), (4, 4, 4), 1, np.float32)]
 
 
 @pytest.mark.parametrize("dims,S,C,dtype", CASES)
