@@ -41,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak with packed FP32 disabled (as this build compiles every
+# FP32 vector peak with packed FP32 disabled (the library compiles every
 # kernel): 256 CUs x 64 lanes x 2 flops per FMA x 2.4 GHz = 78.6 TFLOP/s (the
 # published 157.3 counts packed FP32 dual issue)
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -369,7 +369,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent images shard with no communication; see DESIGN.md)", file=sys.stderr)
+              "(independent images would shard over GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -58,7 +58,7 @@ enum {
   SSLIC_EINVAL = -1,      /* an argument is outside the validity rules */
   SSLIC_ENOMEM = -2,      /* device workspace could not be allocated */
   SSLIC_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed */
-  SSLIC_EUNSUPPORTED = -4 /* valid request this build does not handle */
+  SSLIC_EUNSUPPORTED = -4 /* valid request the library does not handle */
 };
 
 /* Options of sslic_run; a zeroed struct (or NULL) means the defaults. */
