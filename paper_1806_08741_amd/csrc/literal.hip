@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kThreads)
 assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict__ recs,
                       const int* __restrict__ bstart, const int* __restrict__ items,
                       const int* __restrict__ done, int32_t* __restrict__ labels,
-                      float* __restrict__ dist, int64_t nblocks, int first) {
+                      float* __restrict__ dist, uint32_t nblocks, int first) {
   if (*done) return;
   constexpr int CM = CC > 0 ? CC : kMaxChan;
   constexpr int RN = (CM + 3 * ND + 1 + 3) & ~3;  // record words (rec_words)
@@ -69,21 +69,27 @@ assign_persist_kernel(Geo g, const T* __restrict__ img, const float* __restrict_
   const int RS = g.rs;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t tile = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-  const int64_t b = tile * kWaves + wave;
+  const uint32_t tile = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const uint32_t b = tile * kWaves + (uint32_t)wave;
   if (b >= nblocks) return;  // no barrier in this kernel
 
-  // the block (axis 0 fastest over blocks) and this lane's voxel in it
+  // the block (axis 0 fastest over blocks; 32-bit index arithmetic, the
+  // last axis without a division) and this lane's voxel in it
   int org[ND], top[ND], x[ND];
-  int64_t rb = b;
+  uint32_t rb = b;
   int lr = lane;
   bool valid = true;
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     const int Bi = Blk<ND>::B[i];
-    const int nbi = (g.n[i] + Bi - 1) / Bi;
-    org[i] = (int)(rb % nbi) * Bi;
-    rb /= nbi;
+    if (i + 1 < ND) {
+      const uint32_t nbi = (uint32_t)(g.n[i] + Bi - 1) / Bi;
+      const uint32_t q = rb / nbi;
+      org[i] = (int)(rb - q * nbi) * Bi;
+      rb = q;
+    } else {
+      org[i] = (int)rb * Bi;
+    }
     top[i] = min(org[i] + Bi, g.n[i]) - 1;
     x[i] = org[i] + lr % Bi;
     lr /= Bi;
@@ -219,16 +225,16 @@ hipError_t dispatch_c(const Geo& g, const void* img, const Iter& it, int32_t* la
   for (int i = 0; i < ND; ++i) nblocks *= (g.n[i] + Blk<ND>::B[i] - 1) / Blk<ND>::B[i];
   const int64_t nwg = ((nblocks + kWaves - 1) / kWaves + 7) / 8 * 8;  // whole rounds of 8 XCDs
   if (nwg <= 0) return hipSuccess;
-  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;  // 32-bit block indices
   const T* p = (const T*)img;
   const unsigned grid = (unsigned)nwg;
   const float* r = it.ctab;
   const int *bs = it.bin_start, *items = it.bin_items, *done = it.done;
   switch (g.C) {
-    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
-    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
-    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
-    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, nblocks, first); break;
+    case 1: assign_persist_kernel<T, ND, 1><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, (uint32_t)nblocks, first); break;
+    case 3: assign_persist_kernel<T, ND, 3><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, (uint32_t)nblocks, first); break;
+    case 4: assign_persist_kernel<T, ND, 4><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, (uint32_t)nblocks, first); break;
+    default: assign_persist_kernel<T, ND, 0><<<grid, kThreads, 0, s>>>(g, p, r, bs, items, done, labels, dist, (uint32_t)nblocks, first); break;
   }
   return hipGetLastError();
 }
