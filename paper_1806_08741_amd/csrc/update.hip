@@ -38,6 +38,22 @@ __device__ __forceinline__ void add_global_f(const Geo& g, uint64_t* acc, int64_
   atomicAdd(reinterpret_cast<double*>(acc + key * g.F + f), v);
 }
 
+// 2D integer images with 1, 3 or 4 channels pack an LDS entry into few
+// 64-bit words whose fields no tile can overflow: word 0 holds the count
+// (<= 4096, 13 bits) and the sums of the tile-relative coordinates (each
+// <= 4096 * 63, 18 bits) at bits 0, 13 and 31; the channel sums (<= 4096 *
+// 255 in 20 bits for u8, <= 4096 * 65535 in 28 bits for u16) follow, as many
+// to a word as fit.  A run then adds into its entry with 2 or 3 LDS atomics
+// instead of 1 + 2 + C, and the entry is unpacked once per tile.
+template <typename T, int ND, int CC>
+struct Packing {
+  static constexpr bool on = ND == 2 && !std::is_same<T, float>::value && CC > 0 &&
+                             kCols == 64 && kRows == 64;
+  static constexpr int CW = sizeof(T) == 1 ? 20 : 28;
+  static constexpr int PW = 64 / CW;
+  static constexpr int NCW = CC > 0 ? (CC + PW - 1) / PW : 1;
+};
+
 template <typename T, int ND, int CC>
 __global__ void __launch_bounds__(kThreads)
 update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labels, Iter it) {
@@ -60,6 +76,9 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
   const int64_t tile = blockIdx.x;
   const int x = (int)(tile % tiles_x) * kCols + lane;
   const int64_t r0 = (tile / tiles_x) * kRows + (int64_t)wave * kRowsPerWave;
+  using PK = Packing<T, ND, CC>;
+  const uint64_t x_org = (uint64_t)(tile % tiles_x) * kCols;  // tile origin (packed entries)
+  const uint64_t y_org = (uint64_t)(tile / tiles_x) * kRows;
 
   int cur = -1;
   uint32_t cnt = 0;
@@ -72,13 +91,45 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
     if (cur < 0 || cur >= g.K || cnt == 0) return;
     uint32_t h = ((uint32_t)cur * 2654435761u) >> (32 - 8);  // kHash = 256
     int slot = -1;
+    volatile int* vkeys = keys;
     for (int p = 0; p < kHash; ++p) {
-      int old = atomicCAS(&keys[h], -1, cur);
-      if (old == -1 || old == cur) {
+      // a slot that already holds the label needs no atomic; an empty one is
+      // claimed by compare-and-swap (keys are never removed)
+      const int k = vkeys[h];
+      if (k == cur) {
         slot = (int)h;
         break;
       }
+      if (k == -1) {
+        const int old = atomicCAS(&keys[h], -1, cur);
+        if (old == -1 || old == cur) {
+          slot = (int)h;
+          break;
+        }
+      }
       h = (h + 1) & (kHash - 1);
+    }
+    if constexpr (PK::on) {
+      if (slot >= 0) {
+        // the run's coordinate sums are tile-relative here
+        uint64_t* vv = vals + slot * F;
+        atomicAdd(reinterpret_cast<unsigned long long*>(vv),
+                  (unsigned long long)((uint64_t)cnt | sc[0] << 13 | sc[1] << 31));
+        uint64_t cw[PK::NCW];
+#pragma unroll
+        for (int j = 0; j < PK::NCW; ++j) cw[j] = 0;
+#pragma unroll
+        for (int c = 0; c < CC; ++c) cw[c / PK::PW] |= (uint64_t)sch[c] << (PK::CW * (c % PK::PW));
+#pragma unroll
+        for (int j = 0; j < PK::NCW; ++j)
+          atomicAdd(reinterpret_cast<unsigned long long*>(vv + 1 + j), (unsigned long long)cw[j]);
+      } else {
+        add_global(g, it.acc, cur, 0, cnt);
+        add_global(g, it.acc, cur, 1, sc[0] + cnt * x_org);
+        add_global(g, it.acc, cur, 2, sc[1] + cnt * y_org);
+        for (int c = 0; c < C; ++c) add_global(g, it.acc, cur, 1 + ND + c, (uint64_t)sch[c]);
+      }
+      return;
     }
     if (slot >= 0) {
       uint64_t* vv = vals + slot * F;
@@ -133,8 +184,13 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
         for (int c = 0; c < C; ++c) sch[c] = 0;
       }
       ++cnt;
-      sc[0] += (uint64_t)x;
-      for (int i = 1; i < ND; ++i) sc[i] += (uint64_t)y[i];
+      if constexpr (PK::on) {  // tile-relative: lane, and the row within the tile
+        sc[0] += (uint64_t)lane;
+        sc[1] += (uint64_t)(wave * kRowsPerWave + j);
+      } else {
+        sc[0] += (uint64_t)x;
+        for (int i = 1; i < ND; ++i) sc[i] += (uint64_t)y[i];
+      }
       for (int c = 0; c < C; ++c) sch[c] += (CS)val[j][c];
       for (int i = 1; i < ND; ++i) {
         if (++y[i] < g.n[i]) break;
@@ -148,6 +204,18 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
     int key = keys[s];
     if (key < 0) continue;
     const uint64_t* vv = vals + s * F;
+    if constexpr (PK::on) {
+      const uint64_t w0 = vv[0];
+      const uint64_t n = w0 & 0x1fffu;
+      add_global(g, it.acc, key, 0, n);
+      add_global(g, it.acc, key, 1, ((w0 >> 13) & 0x3ffffu) + n * x_org);
+      add_global(g, it.acc, key, 2, ((w0 >> 31) & 0x3ffffu) + n * y_org);
+      constexpr uint64_t m = (1ull << PK::CW) - 1;
+#pragma unroll
+      for (int c = 0; c < CC; ++c)
+        add_global(g, it.acc, key, 1 + ND + c, (vv[1 + c / PK::PW] >> (PK::CW * (c % PK::PW))) & m);
+      continue;
+    }
     add_global(g, it.acc, key, 0, vv[0]);
     for (int i = 0; i < ND; ++i) add_global(g, it.acc, key, 1 + i, vv[1 + i]);
     for (int c = 0; c < C; ++c) {
