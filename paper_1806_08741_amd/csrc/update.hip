@@ -38,20 +38,29 @@ __device__ __forceinline__ void add_global_f(const Geo& g, uint64_t* acc, int64_
   atomicAdd(reinterpret_cast<double*>(acc + key * g.F + f), v);
 }
 
-// 2D integer images with 1, 3 or 4 channels pack an LDS entry into few
-// 64-bit words whose fields no tile can overflow: word 0 holds the count
-// (<= 4096, 13 bits) and the sums of the tile-relative coordinates (each
-// <= 4096 * 63, 18 bits) at bits 0, 13 and 31; the channel sums (<= 4096 *
-// 255 in 20 bits for u8, <= 4096 * 65535 in 28 bits for u16) follow, as many
-// to a word as fit.  A run then adds into its entry with 2 or 3 LDS atomics
-// instead of 1 + 2 + C, and the entry is unpacked once per tile.
+// 2D and 3D integer images with 1, 3 or 4 channels pack an LDS entry into
+// few 64-bit words whose fields no tile can overflow.  The count is <= 4096
+// (13 bits) and the sum of the tile-relative axis-0 coordinates <= 4096 * 63
+// (18 bits); a channel sum is <= 4096 * 255 (20 bits) for u8 and
+// <= 4096 * 65535 (28 bits) for u16.
+//   2D: word 0 = count | sum x << 13 | sum y << 31 (y tile-relative too);
+//   3D: word 0 = count | sum x << 13 | channel 0 << 31, word 1 = sum y |
+//       sum z << 28 (absolute, 28 bits each, so n1 and n2 must be <= 65536;
+//       a tile's rows run over y and z);
+// the other channel sums follow, as many to a word as fit.  A run then adds
+// into its entry with 2 or 3 LDS atomics instead of 1 + ND + C, and the entry
+// is unpacked once per tile.
 template <typename T, int ND, int CC>
 struct Packing {
-  static constexpr bool on = ND == 2 && !std::is_same<T, float>::value && CC > 0 &&
+  static constexpr bool on = (ND == 2 || ND == 3) && !std::is_same<T, float>::value && CC > 0 &&
                              kCols == 64 && kRows == 64;
   static constexpr int CW = sizeof(T) == 1 ? 20 : 28;
   static constexpr int PW = 64 / CW;
-  static constexpr int NCW = CC > 0 ? (CC + PW - 1) / PW : 1;
+  static constexpr int C0 = ND == 3 ? 1 : 0;  // channels in word 0
+  static constexpr int CB = ND == 3 ? 2 : 1;  // first word of the other channels
+  static constexpr int NCW = CC > 0 ? (CC - C0 + PW - 1) / PW : 1;
+  __device__ static int word(int c) { return CB + (c - C0) / PW; }
+  __device__ static int shift(int c) { return CW * ((c - C0) % PW); }
 };
 
 template <typename T, int ND, int CC>
@@ -77,6 +86,7 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
   const int x = (int)(tile % tiles_x) * kCols + lane;
   const int64_t r0 = (tile / tiles_x) * kRows + (int64_t)wave * kRowsPerWave;
   using PK = Packing<T, ND, CC>;
+  const bool pk = PK::on && (ND == 2 || (g.n[1] <= 65536 && g.n[2] <= 65536));
   const uint64_t x_org = (uint64_t)(tile % tiles_x) * kCols;  // tile origin (packed entries)
   const uint64_t y_org = (uint64_t)(tile / tiles_x) * kRows;
 
@@ -110,26 +120,38 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
       h = (h + 1) & (kHash - 1);
     }
     if constexpr (PK::on) {
-      if (slot >= 0) {
-        // the run's coordinate sums are tile-relative here
-        uint64_t* vv = vals + slot * F;
-        atomicAdd(reinterpret_cast<unsigned long long*>(vv),
-                  (unsigned long long)((uint64_t)cnt | sc[0] << 13 | sc[1] << 31));
-        uint64_t cw[PK::NCW];
+      if (pk) {
+        // the run's axis-0 sum is tile-relative here (and in 2D its y sum)
+        if (slot >= 0) {
+          uint64_t w[PK::CB + PK::NCW];
 #pragma unroll
-        for (int j = 0; j < PK::NCW; ++j) cw[j] = 0;
+          for (int j = 0; j < PK::CB + PK::NCW; ++j) w[j] = 0;
+          w[0] = (uint64_t)cnt | sc[0] << 13;
+          if constexpr (ND == 2) {
+            w[0] |= sc[1] << 31;
+          } else {
+            w[0] |= (uint64_t)sch[0] << 31;
+            w[1] = sc[1] | sc[2] << 28;
+          }
 #pragma unroll
-        for (int c = 0; c < CC; ++c) cw[c / PK::PW] |= (uint64_t)sch[c] << (PK::CW * (c % PK::PW));
+          for (int c = PK::C0; c < CC; ++c) w[PK::word(c)] |= (uint64_t)sch[c] << PK::shift(c);
+          uint64_t* vv = vals + slot * F;
 #pragma unroll
-        for (int j = 0; j < PK::NCW; ++j)
-          atomicAdd(reinterpret_cast<unsigned long long*>(vv + 1 + j), (unsigned long long)cw[j]);
-      } else {
-        add_global(g, it.acc, cur, 0, cnt);
-        add_global(g, it.acc, cur, 1, sc[0] + cnt * x_org);
-        add_global(g, it.acc, cur, 2, sc[1] + cnt * y_org);
-        for (int c = 0; c < C; ++c) add_global(g, it.acc, cur, 1 + ND + c, (uint64_t)sch[c]);
+          for (int j = 0; j < PK::CB + PK::NCW; ++j)
+            atomicAdd(reinterpret_cast<unsigned long long*>(vv + j), (unsigned long long)w[j]);
+        } else {
+          add_global(g, it.acc, cur, 0, cnt);
+          add_global(g, it.acc, cur, 1, sc[0] + cnt * x_org);
+          if constexpr (ND == 2) {
+            add_global(g, it.acc, cur, 2, sc[1] + cnt * y_org);
+          } else {
+            add_global(g, it.acc, cur, 2, sc[1]);
+            add_global(g, it.acc, cur, 3, sc[2]);
+          }
+          for (int c = 0; c < C; ++c) add_global(g, it.acc, cur, 1 + ND + c, (uint64_t)sch[c]);
+        }
+        return;
       }
-      return;
     }
     if (slot >= 0) {
       uint64_t* vv = vals + slot * F;
@@ -184,9 +206,10 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
         for (int c = 0; c < C; ++c) sch[c] = 0;
       }
       ++cnt;
-      if constexpr (PK::on) {  // tile-relative: lane, and the row within the tile
+      if (pk) {  // tile-relative axis 0 (and, in 2D, the row within the tile)
         sc[0] += (uint64_t)lane;
-        sc[1] += (uint64_t)(wave * kRowsPerWave + j);
+        if constexpr (ND == 2) sc[1] += (uint64_t)(wave * kRowsPerWave + j);
+        else for (int i = 1; i < ND; ++i) sc[i] += (uint64_t)y[i];
       } else {
         sc[0] += (uint64_t)x;
         for (int i = 1; i < ND; ++i) sc[i] += (uint64_t)y[i];
@@ -205,16 +228,24 @@ update_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ labe
     if (key < 0) continue;
     const uint64_t* vv = vals + s * F;
     if constexpr (PK::on) {
-      const uint64_t w0 = vv[0];
-      const uint64_t n = w0 & 0x1fffu;
-      add_global(g, it.acc, key, 0, n);
-      add_global(g, it.acc, key, 1, ((w0 >> 13) & 0x3ffffu) + n * x_org);
-      add_global(g, it.acc, key, 2, ((w0 >> 31) & 0x3ffffu) + n * y_org);
-      constexpr uint64_t m = (1ull << PK::CW) - 1;
+      if (pk) {
+        const uint64_t w0 = vv[0];
+        const uint64_t n = w0 & 0x1fffu;
+        constexpr uint64_t m = (1ull << PK::CW) - 1;
+        add_global(g, it.acc, key, 0, n);
+        add_global(g, it.acc, key, 1, ((w0 >> 13) & 0x3ffffu) + n * x_org);
+        if constexpr (ND == 2) {
+          add_global(g, it.acc, key, 2, ((w0 >> 31) & 0x3ffffu) + n * y_org);
+        } else {
+          add_global(g, it.acc, key, 2, vv[1] & 0xfffffffu);
+          add_global(g, it.acc, key, 3, vv[1] >> 28);
+          add_global(g, it.acc, key, 1 + ND, (w0 >> 31) & m);
+        }
 #pragma unroll
-      for (int c = 0; c < CC; ++c)
-        add_global(g, it.acc, key, 1 + ND + c, (vv[1 + c / PK::PW] >> (PK::CW * (c % PK::PW))) & m);
-      continue;
+        for (int c = PK::C0; c < CC; ++c)
+          add_global(g, it.acc, key, 1 + ND + c, (vv[PK::word(c)] >> PK::shift(c)) & m);
+        continue;
+      }
     }
     add_global(g, it.acc, key, 0, vv[0]);
     for (int i = 0; i < ND; ++i) add_global(g, it.acc, key, 1 + i, vv[1 + i]);

@@ -134,6 +134,27 @@ def test_update_one_step(ctx, name, dims, S, m):
     assert got_e == pytest.approx(exp_e, rel=1e-9)
 
 
+@pytest.mark.parametrize("dims", [(37, 29, 23), (70, 45), (130, 3, 70)])
+@pytest.mark.parametrize("dtype,C", [(np.uint8, 1), (np.uint8, 3), (np.uint8, 4),
+                                     (np.uint16, 1), (np.uint16, 3), (np.uint16, 4)])
+def test_update_packed_entries(ctx, dims, dtype, C):
+    """2D and 3D integer images with 1, 3 or 4 channels (the packed LDS
+    entries of the map step), on coherent labels and on random ones that
+    fill the table: bit-exact."""
+    nd = len(dims)
+    S = (6,) * nd
+    img = rand_image(dims, C, dtype, 11)
+    cen0 = oracle.seed(img, nd, S)
+    lab = oracle.grid_labels(dims, S)
+    oracle.assign(img, nd, S, 10.0, cen0, lab)
+    rng = np.random.default_rng(3)
+    for labels in (lab, rng.integers(0, cen0.shape[0], lab.size).astype(np.int32)):
+        exp_c, exp_n, _ = oracle.update(img, nd, S, 10.0, labels, cen0)
+        got_c, got_n, _ = ctx.update(dev(img), S, 10.0, dev(labels), dev(cen0))
+        np.testing.assert_array_equal(host(got_n), exp_n)
+        np.testing.assert_array_equal(host(got_c), exp_c)
+
+
 def test_update_arbitrary_labels(ctx):
     """Random labels (no spatial coherence) and labels outside [0, K) that
     must be ignored: the LDS table overflows into global atomics."""
