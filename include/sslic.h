@@ -27,9 +27,13 @@
  * Clusters.  K = prod_i K_i with K_i = max(1, round-half-up(N_i / S_i));
  *   cluster k has grid index j_i with k = sum_i j_i prod_{i'<i} K_i' and its
  *   seed at floor((2 j_i + 1) N_i / (2 K_i)) (Sec. 2.2 "fixed intervals").
- * Validity.  1 <= ndim <= 4; every N_i >= 1; prod N_i < 2^31;
- *   1 <= channels <= 8; every S_i >= 1; m > 0 and finite; iterations >= 1;
- *   K < 2^31 - N.  Everything is checked before any work is enqueued.
+ * Validity.  1 <= ndim <= 4; every N_i >= 1; prod N_i < 2^40;
+ *   1 <= channels <= 8; 1 <= S_i <= 2^30; m > 0 and finite; iterations >= 1.
+ *   Violations return SSLIC_EINVAL.  Valid requests this build does not
+ *   handle return SSLIC_EUNSUPPORTED: images of 2^31 voxels or more (voxel,
+ *   cluster and label indices are 32-bit inside the kernels) and K + N of
+ *   2^31 or more (new labels K, K+1, ... must fit int32).  Everything is
+ *   checked before any work is enqueued.
  * Asynchrony.  All device work is enqueued on `stream` (0 = the null stream);
  *   an entry point returns as soon as the work is queued, unless a host
  *   `*_out` pointer is given, which makes it wait for `stream`.

@@ -58,11 +58,22 @@ int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, con
     int64_t s = i < ndim ? S[i] : 1;
     if (n < 1) return fail(SSLIC_EINVAL, "dims[%d] = %lld < 1", i, (long long)n);
     if (s < 1) return fail(SSLIC_EINVAL, "S[%d] = %lld < 1", i, (long long)s);
-    if (n > (1LL << 31) || s > (1LL << 30)) return fail(SSLIC_EINVAL, "axis %d too large", i);
+    if (s > (1LL << 30)) return fail(SSLIC_EINVAL, "S[%d] = %lld is above 2^30", i, (long long)s);
+    if (n > ((1LL << 40) - 1) / N) return fail(SSLIC_EINVAL, "image has 2^40 voxels or more");
+    N *= n;
+  }
+  // Valid up to 2^40 voxels; the kernels index voxels, clusters and new labels
+  // in 32 bits, so larger images are refused as unsupported.
+  if (N >= (1LL << 31))
+    return fail(SSLIC_EUNSUPPORTED, "images of 2^31 voxels or more are not supported (%lld voxels)",
+                (long long)N);
+  N = 1;
+  for (int i = 0; i < kMaxDim; ++i) {
+    int64_t n = i < ndim ? dims[i] : 1;
+    int64_t s = i < ndim ? S[i] : 1;
     g->n[i] = (int)n;
     g->st[i] = N;
     N *= n;
-    if (N >= (1LL << 31)) return fail(SSLIC_EINVAL, "image has 2^31 voxels or more");
     g->S[i] = (int)s;
     g->Ka[i] = (int)grid_count(n, s);
     K *= g->Ka[i];
@@ -76,7 +87,8 @@ int make_geo(Geo* g, int ndim, const int64_t* dims, int channels, int dtype, con
   }
   g->N = N;
   g->K = K_override > 0 ? K_override : K;
-  if (g->K + N >= (1LL << 31)) return fail(SSLIC_EINVAL, "K + N must stay below 2^31");
+  if (g->K + N >= (1LL << 31))
+    return fail(SSLIC_EUNSUPPORTED, "K + N must stay below 2^31 (labels K, K+1, ... are int32)");
   g->nbins = nbins;
   g->prodS = prodS;
   g->rs = rec_words(channels, g->nd);
@@ -183,23 +195,17 @@ hipEvent_t next_event(sslic_ctx* ctx) {
   return ctx->ev_pool[ctx->ev_used++];
 }
 
-// Brackets the launches of one kernel class with events when profiling.
-struct Mark {
-  sslic_ctx* ctx;
-  const char* name;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  Mark(sslic_ctx* c, const char* n, hipStream_t st) : ctx(c), name(n), s(st) {
-    if (ctx && ctx->prof && (a = next_event(ctx))) (void)hipEventRecord(a, s);
-  }
-  ~Mark() {
-    if (!a) return;
-    hipEvent_t b = next_event(ctx);
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    ctx->marks[name].emplace_back(a, b);
-  }
-};
+Mark::Mark(sslic_ctx* c, const char* n, hipStream_t st) : ctx(c), name(n), s(st) {
+  if (ctx && ctx->prof && (a = next_event(ctx))) (void)hipEventRecord(a, s);
+}
+
+Mark::~Mark() {
+  if (!a) return;
+  hipEvent_t b = next_event(ctx);
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  ctx->marks[name].emplace_back(a, b);
+}
 
 // Copy device int32 scalars to host outputs (waits for the stream).
 int read_ints(sslic_ctx* ctx, hipStream_t s, const int32_t* dev_a, int32_t* out_a,

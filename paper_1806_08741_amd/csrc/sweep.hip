@@ -417,17 +417,17 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
   };
 
   // The meeting centres of a block, one at a time (their records are scalar
-  // loads at byte offset readlane(jo, l)).  Centres whose window covers the
+  // loads of record readlane(jr, l), addressed in 64 bits).  Centres whose window covers the
   // whole block (mask mf) need no window test; for the others (mask mc) the
   // closed window is tested on every axis as one unsigned range compare.
-  auto scan = [&](uint64_t mf, uint64_t mc, int jo, const int* x, const float* xs,
+  auto scan = [&](uint64_t mf, uint64_t mc, int jr, const int* x, const float* xs,
                   const float* I, bool tagl, uint64_t& bkey) {
     constexpr int RF = CM + ND + 1;  // mu, c', k
     while (mf) {
       const int l = (int)__builtin_ctzll(mf);
       mf &= mf - 1;
-      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
-      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(recs) + o);
+      const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane(jr, l);
+      const float* rec = recs + (uint64_t)rk * (uint32_t)RS;
       float R[RF];
 #pragma unroll
       for (int w = 0; w < RF; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
@@ -448,8 +448,8 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
     while (mc) {
       const int l = (int)__builtin_ctzll(mc);
       mc &= mc - 1;
-      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane(jo, l);
-      const float* rec = reinterpret_cast<const float*>(reinterpret_cast<const char*>(recs) + o);
+      const uint32_t rk = (uint32_t)__builtin_amdgcn_readlane(jr, l);
+      const float* rec = recs + (uint64_t)rk * (uint32_t)RS;
       float R[RN];
 #pragma unroll
       for (int w = 0; w < RN; ++w) R[w] = (CC > 0 || w < RS) ? rec[w] : 0.0f;
@@ -547,7 +547,6 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
         hhi[i] = irec[rec_hi(C, ND) + i];
       }
     }
-    const int hjo = hrk * RS * 4;
 
     // This lane's voxel in block 0 of the row; block bx is B_0 * bx voxels
     // further along axis 0.  Lanes outside the image read (and never write)
@@ -600,7 +599,7 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
         } else {
           test(held, hlo, hhi, blo, bhi, mf, mc);
         }
-        scan(mf, mc, hjo, x, xs, I, TBL, bkey);
+        scan(mf, mc, hrk, x, xs, I, TBL, bkey);
       } else {
         int b0[ND], b1[ND];
         for (int i = 0; i < ND; ++i) {
@@ -620,7 +619,7 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
           }
           uint64_t mf, mc;
           test(bheld, lo, hi, blo, bhi, mf, mc);
-          scan(mf, mc, bk0 * RS * 4, x, xs, I, false, bkey);
+          scan(mf, mc, bk0, x, xs, I, false, bkey);
         } else {
           // more centres than lanes (a crowded neighbourhood): each lane walks them
           int rc[ND];

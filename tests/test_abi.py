@@ -6,6 +6,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -55,13 +56,39 @@ def test_num_clusters_host_only(lib):
 
 @pytest.mark.parametrize("ndim,dims,S,msg", [
     (0, [4], [1], "ndim"), (5, [2] * 5, [1] * 5, "ndim"), (2, [0, 4], [1, 1], "dims"),
-    (2, [4, 4], [0, 1], "S"), (2, [1 << 16, 1 << 16], [1, 1], "2^31")])
+    (2, [4, 4], [0, 1], "S"), (2, [1 << 20, 1 << 20], [1, 1], "2^40"),
+    (3, [1 << 30, 1 << 30, 1 << 30], [8, 8, 8], "2^40"), (2, [4, 4], [(1 << 31) - 1, 1], "S")])
 def test_num_clusters_rejects(lib, ndim, dims, S, msg):
     from paper_1806_08741_amd import sslic
     k = ctypes.c_int64(0)
     rc = lib.sslic_num_clusters(ndim, sslic._i64(dims), sslic._i32(S), ctypes.byref(k), None)
     assert rc == -1
     assert msg in lib.sslic_last_error().decode()
+
+
+@pytest.mark.parametrize("dims,S", [([1 << 16, 1 << 16], [16, 16]), ([2048, 1216, 1978], [50] * 3),
+                                    ([1 << 16, 1 << 15], [1, 1]), ([1 << 15, 1 << 15], [1, 1])])
+def test_large_images_unsupported_before_any_device_work(lib, dims, S):
+    """Images of 2^31 voxels or more (valid up to 2^40), and K + N of 2^31 or
+    more, are refused with SSLIC_EUNSUPPORTED by every entry point before the
+    context or any device pointer is used (a dummy context suffices).  The
+    second case is the paper's 2048 x 1216 x 1978 volume."""
+    from paper_1806_08741_amd import sslic
+    k = ctypes.c_int64(0)
+    rc = lib.sslic_num_clusters(len(dims), sslic._i64(dims), sslic._i32(S), ctypes.byref(k), None)
+    assert rc == -4, lib.sslic_last_error().decode()
+    dummy = ctypes.create_string_buffer(64)
+    ctxp = ctypes.cast(dummy, ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x1000)
+    o = sslic._Options(0.0, 0, None, None, None, None)
+    rc = lib.sslic_run(ctxp, fake, len(dims), sslic._i64(dims), 1, 1, sslic._i32(S), 10.0, 5,
+                       ctypes.byref(o), fake, fake, None, None, None, None)
+    assert rc == -4
+    assert "2^31" in lib.sslic_last_error().decode()
+    if np.prod(dims) >= 1 << 31:  # with K = 1000 given, only N itself is too large
+        rc = lib.sslic_assign(ctxp, fake, len(dims), sslic._i64(dims), 1, 1, sslic._i32(S), 10.0,
+                              fake, 1000, fake, None)
+        assert rc == -4
 
 
 def test_run_validates_before_any_device_work(lib):
