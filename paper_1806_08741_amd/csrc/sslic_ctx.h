@@ -66,6 +66,19 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L);
 CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N);
 int select_device(sslic_ctx* ctx);
 
+// Brackets the launches of one kernel class with events when profiling
+// (sslic_profile.h); a no-op unless the context's profiling is on.
+struct Mark {
+  sslic_ctx* ctx;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Mark(sslic_ctx* c, const char* n, hipStream_t st);
+  ~Mark();
+  Mark(const Mark&) = delete;
+  Mark& operator=(const Mark&) = delete;
+};
+
 // the batched form behind sslic_run_batch (batch.hip)
 int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic_options* opt,
               int32_t* n_labels_out, hipStream_t s);
