@@ -69,6 +69,12 @@ WORKLOADS = {
         "bisector distance to the second-nearest seed is < 1 voxel get mean 600 "
         "(2-voxel membranes); noise sigma 800; rint, clip [0,65535]",
         {"ranges": ((2000, 50000),), "sigma": 800.0, "membrane": 600.0}),
+    "lab-2k": Workload(
+        "lab-2k", (2048, 1216), 3, torch.float32, (50, 50), 10.0, 5, True, 1000,
+        "Voronoi of 1000 uniform seeds; region mean L~U[0,100], a~U[-86.185,98.254], "
+        "b~U[-107.863,94.482] (the CIE-Lab ranges of 8-bit sRGB); noise sigma 2; "
+        "float32, clip to those ranges",
+        {"ranges": ((0.0, 100.0), (-86.185, 98.254), (-107.863, 94.482)), "sigma": 2.0}),
 }
 
 
@@ -274,6 +280,14 @@ def workload_image(name: str, device, dims: Optional[Sequence[int]] = None, inde
         means = rng.uniform(lo, hi, size=(ns, 1))
         return voronoi_image(dims, 1, torch.uint16, ns, means, w.extra["sigma"], key, device,
                              clip=(0.0, 65535.0), membrane=w.extra["membrane"])
+    if name == "lab-2k":
+        r = w.extra["ranges"]
+        means = np.stack([rng.uniform(lo, hi, size=ns) for lo, hi in r], 1)
+        img = voronoi_image(dims, 3, torch.float32, ns, means, w.extra["sigma"], key, device,
+                            clip=(-200.0, 200.0))
+        lo = torch.tensor([a for a, _ in r], dtype=torch.float32, device=img.device)
+        hi = torch.tensor([b for _, b in r], dtype=torch.float32, device=img.device)
+        return torch.maximum(torch.minimum(img, hi), lo)
     raise KeyError(name)
 
 

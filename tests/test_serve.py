@@ -78,3 +78,41 @@ def test_admission_keeps_to_the_budget():
     assert 0 < srv.peak_used <= budget
     with pytest.raises(ValueError):
         serve.Server(hbm_budget=biggest - 1, lanes=1).serve(reqs, closed_loop=True)
+
+
+@pytest.mark.gpu
+def test_served_against_oracle():
+    """One served request of each kind (2D RGB uint8, 3D uint16, 3D 4-channel
+    float32) against the FP64 oracle: at least 99% of labels agree with the
+    oracle's whole run (as for single images), and the served centres are the
+    member means of the served labels (the oracle's update of those labels
+    returns them: bit-exact for integer images, 1e-6 relative for float)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    trace = synth.request_trace(400.0, 40, key=7, scale=0.12)
+    reqs = serve.make_requests(trace, synth.request_image, "cuda")
+    srv = serve.Server(hbm_budget=1 << 30, lanes=3, max_batch=8)
+    srv.warm(reqs)
+    srv.serve(reqs, closed_loop=True)
+    torch.cuda.synchronize()
+    kinds = {}
+    for r, (_, sp) in zip(reqs, trace):
+        if sp.kind not in kinds or r.voxels < kinds[sp.kind][0].voxels:
+            kinds[sp.kind] = (r, sp)
+    assert set(kinds) == {"rgb2d", "u16-3d", "f32x4-3d"}
+    for kind, (r, sp) in sorted(kinds.items()):
+        img = r.image.cpu().numpy()
+        nd = len(sp.dims)
+        print(f"[case] served {kind} {sp.dims} S={sp.S}", flush=True)
+        ref = oracle.run(img, nd, sp.S, sp.m, sp.iterations, connectivity=False)
+        lab = r.out["labels"].cpu().numpy()
+        cen = r.out["centres"].cpu().numpy()
+        agree = float(np.mean(lab == ref["labels"]))
+        assert agree >= 0.99, (kind, agree)
+        exp_c, exp_n, _ = oracle.update(img, nd, sp.S, sp.m, lab, cen)
+        np.testing.assert_array_equal(r.out["counts"].cpu().numpy(), exp_n)
+        if img.dtype == np.float32:
+            np.testing.assert_allclose(cen, exp_c, rtol=1e-6, atol=1e-9)
+        else:
+            np.testing.assert_array_equal(cen, exp_c)
