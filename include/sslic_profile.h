@@ -1,9 +1,12 @@
 /*
  * sslic_profile.h -- per-kernel timing of libsslic.so with HIP events.
- * While enabled on a context, every launch of a kernel class ("seed",
- * "bins", "assign", "update", "finalize", "connectivity") is bracketed by a
- * pair of hipEvents recorded on the launch stream.  Same conventions as
- * sslic.h (SSLIC_OK or a negative code, sslic_last_error()).
+ * While enabled on a context, every launch of a kernel class of sslic_run
+ * ("seed", "bins", "sweep", "assign_persist", "update", "finalize",
+ * "connectivity") and of sslic_run_batch enqueued directly, not from a
+ * graph ("sweep_batch", "finalize_batch": one launch per group of images of
+ * one kind) is bracketed by a pair of hipEvents recorded on the launch
+ * stream.  Same conventions as sslic.h (SSLIC_OK or a negative code,
+ * sslic_last_error()).
  */
 #ifndef SSLIC_PROFILE_H
 #define SSLIC_PROFILE_H

@@ -198,8 +198,10 @@ struct Plan {
   BLayout L{};
 };
 
-// everything enqueued for one batch (captured or direct)
-int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
+// everything enqueued for one batch (captured or direct); `timed`: bracket
+// the sweep and reduce launches with profiling events (direct launches only)
+int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q, bool timed) {
+  sslic_ctx* mctx = timed ? ctx : nullptr;
   char* b = ctx->bws;
   const BImg* imgs = reinterpret_cast<const BImg*>(b + P.L.imgs);
   const int32_t* cl_img = reinterpret_cast<const int32_t*>(b + P.L.cl_img);
@@ -245,12 +247,15 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q) {
       // with the next tile's start (measured faster than a grid that walks
       // several tiles per workgroup)
       const unsigned grid = (unsigned)g.ntiles;
+      Mark mk(mctx, "sweep_batch", q);
       HIP_TRY(launch_sweep_batch(g.dtype, g.nd, g.C, g.var, imgs, tile_img, g.tile0, g.ntiles,
                                  it.bin_start, it.bin_items, it.ctab, t, grid, q));
     }
-    for (const Group& g : P.groups)
+    for (const Group& g : P.groups) {
+      Mark mk(mctx, "finalize_batch", q);
       HIP_TRY(launch_finalize_batch(g.dtype, g.nd, g.C, imgs, cl_img, g.k0, g.k1, ctab, it.bin_of,
                                     it.bin_cnt, t, q));
+    }
     HIP_TRY(launch_residual_finish_batch(imgs, P.n, t, q));
   }
   HIP_TRY(launch_batch_outputs(imgs, P.n, q));
@@ -455,7 +460,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
     if (use_graph) {
       if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
       HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-      rc = enqueue(ctx, P, ctx->cap_stream);
+      rc = enqueue(ctx, P, ctx->cap_stream, false);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
       if (rc) {
@@ -471,7 +476,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       ctx->bkey = key;
       HIP_TRY(hipGraphLaunch(exec, s));
     } else {
-      if ((rc = enqueue(ctx, P, s))) return rc;
+      if ((rc = enqueue(ctx, P, s, true))) return rc;
     }
   }
 
