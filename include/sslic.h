@@ -126,6 +126,34 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims,
               const sslic_options* opt, int32_t* labels, double* centres, int64_t* counts,
               int32_t* n_labels_out, int32_t* iters_done_out, sslic_stream_t stream);
 
+/* Size of the device scratch of sslic_run_static, per GPU. */
+#define SSLIC_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* sslic_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * allocates nothing (no hipMalloc, hipFree or pinned host memory) and needs
+ * no context: its workspace is a static device array of
+ * SSLIC_STATIC_SCRATCH_BYTES (64 MiB) that the library holds on every GPU it
+ * runs on until the process ends; its device address is looked up once per
+ * device, on the first call there.
+ *   Arguments, outputs and results are those of sslic_run, except that the
+ *   label count and the iterations run are returned only through
+ *   opt->n_labels_dev and opt->iters_done_dev (device int32, may be NULL), so
+ *   the call never waits for `stream`.  The work runs on the calling
+ *   thread's current HIP device; `stream` must belong to it.
+ *   A request whose workspace (as given under sslic_run; e.g. about 16.6 MiB
+ *   for a 1024 x 1024 RGB image at S = 16 with connectivity) exceeds the
+ *   scratch returns SSLIC_ENOMEM before any device work, with the size in
+ *   the message; use sslic_run for it.
+ *   Every call on one GPU shares that GPU's scratch and leaves its contents
+ *   behind (each call clears what must start at zero): calls that overlap on
+ *   one GPU, on any streams or threads, race and give undefined results, so
+ *   serialise them (one stream, or events between streams). */
+int sslic_run_static(const void* image, int ndim, const int64_t* dims, int channels,
+                     sslic_dtype dtype, const int32_t* S, double m, int iterations,
+                     const sslic_options* opt, int32_t* labels, double* centres, int64_t* counts,
+                     sslic_stream_t stream);
+
 /* One image of a batch. */
 typedef struct {
   const void* image;  /* device */

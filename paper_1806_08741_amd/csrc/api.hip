@@ -149,9 +149,8 @@ int ensure_ws(sslic_ctx* ctx, size_t need) {
   return SSLIC_OK;
 }
 
-Iter iter_view(sslic_ctx* ctx, const Layout& L) {
+Iter iter_view(char* b, const Layout& L) {
   Iter it;
-  char* b = ctx->ws;
   it.ctab = (float*)(b + L.ctab);
   it.bin_of = (int32_t*)(b + L.bin_of);
   it.bin_cnt = (int32_t*)(b + L.bin_cnt);
@@ -167,9 +166,8 @@ Iter iter_view(sslic_ctx* ctx, const Layout& L) {
   return it;
 }
 
-CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N) {
+CCBuf cc_view(char* b, const Layout& L, int64_t N) {
   CCBuf c;
-  char* b = ctx->ws;
   c.parent = (int32_t*)(b + L.cc_parent);
   c.size = (int32_t*)(b + L.cc_size);
   c.newlab = (int32_t*)(b + L.cc_newlab);
@@ -179,7 +177,7 @@ CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N) {
   return c;
 }
 
-int32_t* nlab_slot(sslic_ctx* ctx, const Layout& L) { return (int32_t*)(ctx->ws + L.flags) + 3; }
+int32_t* nlab_slot(char* base, const Layout& L) { return (int32_t*)(base + L.flags) + 3; }
 
 int select_device(sslic_ctx* ctx) {
   HIP_TRY(hipSetDevice(ctx->device));
@@ -264,7 +262,88 @@ int run_iterations(sslic_ctx* ctx, const Geo& g, const Iter& it, const void* ima
   return SSLIC_OK;
 }
 
+// The whole filter on a workspace laid out by `L` at device address `ws`:
+// seeding (or the given centres), the iteration loop, then connectivity.  The
+// label count and the iterations run stay on the device (flags of `ws`), and
+// go to opt's device outputs when given.  `ctx` only brackets launches for
+// the profiler and may be null.
+int run_on(sslic_ctx* ctx, char* ws, const Layout& L, const Geo& g, const void* image,
+           int iterations, const sslic_options& o, int32_t* labels, double* centres,
+           int64_t* counts, hipStream_t s) {
+  Iter it = iter_view(ws, L);
+  if (o.init_centres) {
+    if (o.init_centres != centres)
+      HIP_TRY(hipMemcpyAsync(centres, o.init_centres, (size_t)g.K * g.row * 8,
+                             hipMemcpyDeviceToDevice, s));
+  } else {
+    Mark mk(ctx, "seed", s);
+    HIP_TRY(launch_seed(g, image, centres, s));
+  }
+  float* dist = o.persist_distance ? reinterpret_cast<float*>(ws + L.dist) : nullptr;
+  int rc = run_iterations(ctx, g, it, image, iterations, o.tol, labels, centres, counts,
+                          o.residuals, dist, s);
+  if (rc) return rc;
+  int32_t* nl = nlab_slot(ws, L);
+  if (!o.no_connectivity) {
+    Mark mk(ctx, "connectivity", s);
+    HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ws, L, g.N), nl, s));
+  } else {
+    HIP_TRY(launch_fill_i32(nl, (int32_t)g.K, 1, s));
+  }
+  if (o.n_labels_dev) HIP_TRY(hipMemcpyAsync(o.n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
+  if (o.iters_done_dev)
+    HIP_TRY(hipMemcpyAsync(o.iters_done_dev, it.iters, 4, hipMemcpyDeviceToDevice, s));
+  return SSLIC_OK;
+}
+
+// Checks of sslic_run's arguments that need no device (shared with
+// sslic_run_static).
+int check_run(const void* image, int ndim, const int64_t* dims, int channels, int dtype,
+              const int32_t* S, double m, int iterations, const sslic_options* opt,
+              const int32_t* labels, const double* centres, Geo* g, sslic_options* o) {
+  if (!image || !labels || !centres) return fail(SSLIC_EINVAL, "image, labels and centres must be given");
+  if (iterations < 1) return fail(SSLIC_EINVAL, "iterations %d < 1", iterations);
+  *o = sslic_options{};
+  if (opt) *o = *opt;
+  if (!(o->tol >= 0.0)) return fail(SSLIC_EINVAL, "tol must be >= 0");
+  return make_geo(g, ndim, dims, channels, dtype, S, m, 0);
+}
+
 }  // namespace sslic
+
+// ---- the entry point that allocates nothing (sslic_run_static) -------------
+//
+// Its workspace is this array: one copy on every GPU the library runs on,
+// held until the process ends.  On the host `scratch` is only a stand-in for
+// the symbol, not a device address: host code looks up the array's address
+// on each device once (static_scratch) and passes that address to kernels
+// and copies, never the name itself.
+static __device__ __align__(256) char scratch[SSLIC_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};  // device address of `scratch`, per device ordinal
+
+// The device address of `scratch` on `device` (the current device).
+int static_scratch(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(SSLIC_EUNSUPPORTED, "device ordinal %d above %d", device, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(SSLIC_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    }
+    g_scratch[device] = static_cast<char*>(p);
+  }
+  *out = g_scratch[device];
+  return SSLIC_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -319,13 +398,10 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
               const sslic_options* opt, int32_t* labels, double* centres, int64_t* counts,
               int32_t* n_labels_out, int32_t* iters_done_out, sslic_stream_t stream) {
   if (!ctx) return fail(SSLIC_EINVAL, "ctx is NULL");
-  if (!image || !labels || !centres) return fail(SSLIC_EINVAL, "image, labels and centres must be given");
-  if (iterations < 1) return fail(SSLIC_EINVAL, "iterations %d < 1", iterations);
-  sslic_options o{};
-  if (opt) o = *opt;
-  if (!(o.tol >= 0.0)) return fail(SSLIC_EINVAL, "tol must be >= 0");
   Geo g;
-  int rc = make_geo(&g, ndim, dims, channels, dtype, S, m, 0);
+  sslic_options o;
+  int rc = check_run(image, ndim, dims, channels, dtype, S, m, iterations, opt, labels, centres,
+                     &g, &o);
   if (rc) return rc;
   if ((rc = select_device(ctx))) return rc;
   const bool cc = !o.no_connectivity;
@@ -333,29 +409,33 @@ int sslic_run(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dims, 
   Layout L = layout(g, iterations, cc, !persist, persist);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  Iter it = iter_view(ctx, L);
-  if (o.init_centres) {
-    if (o.init_centres != centres)
-      HIP_TRY(hipMemcpyAsync(centres, o.init_centres, (size_t)g.K * g.row * 8,
-                             hipMemcpyDeviceToDevice, s));
-  } else {
-    Mark mk(ctx, "seed", s);
-    HIP_TRY(launch_seed(g, image, centres, s));
-  }
-  float* dist = persist ? reinterpret_cast<float*>(ctx->ws + L.dist) : nullptr;
-  if ((rc = run_iterations(ctx, g, it, image, iterations, o.tol, labels, centres, counts,
-                           o.residuals, dist, s)))
-    return rc;
-  int32_t* nl = nlab_slot(ctx, L);
-  if (cc) {
-    Mark mk(ctx, "connectivity", s);
-    HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L, g.N), nl, s));
-  } else {
-    HIP_TRY(launch_fill_i32(nl, (int32_t)g.K, 1, s));
-  }
-  if (o.n_labels_dev) HIP_TRY(hipMemcpyAsync(o.n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
-  if (o.iters_done_dev) HIP_TRY(hipMemcpyAsync(o.iters_done_dev, it.iters, 4, hipMemcpyDeviceToDevice, s));
-  return read_ints(ctx, s, nl, n_labels_out, it.iters, iters_done_out);
+  if ((rc = run_on(ctx, ctx->ws, L, g, image, iterations, o, labels, centres, counts, s))) return rc;
+  return read_ints(ctx, s, nlab_slot(ctx->ws, L), n_labels_out, iter_view(ctx->ws, L).iters,
+                   iters_done_out);
+}
+
+int sslic_run_static(const void* image, int ndim, const int64_t* dims, int channels,
+                     sslic_dtype dtype, const int32_t* S, double m, int iterations,
+                     const sslic_options* opt, int32_t* labels, double* centres, int64_t* counts,
+                     sslic_stream_t stream) {
+  Geo g;
+  sslic_options o;
+  int rc = check_run(image, ndim, dims, channels, dtype, S, m, iterations, opt, labels, centres,
+                     &g, &o);
+  if (rc) return rc;
+  const bool persist = o.persist_distance != 0;
+  const Layout L = layout(g, iterations, !o.no_connectivity, !persist, persist);
+  if (L.total > (size_t)SSLIC_STATIC_SCRATCH_BYTES)
+    return fail(SSLIC_ENOMEM,
+                "sslic_run_static: this request needs %zu bytes of workspace, above the static "
+                "scratch of %zu bytes (use sslic_run)",
+                L.total, (size_t)SSLIC_STATIC_SCRATCH_BYTES);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  char* ws = nullptr;
+  if ((rc = static_scratch(device, &ws))) return rc;
+  return run_on(nullptr, ws, L, g, image, iterations, o, labels, centres, counts,
+                (hipStream_t)stream);
 }
 
 int sslic_run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic_options* opt,
@@ -399,7 +479,7 @@ int sslic_assign(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   Layout L = layout(g, 1, false, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  Iter it = iter_view(ctx, L);
+  Iter it = iter_view(ctx->ws, L);
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_prep(g, centres, it, s));
@@ -427,7 +507,7 @@ int sslic_assign_persist(sslic_ctx* ctx, const void* image, int ndim, const int6
   Layout L = layout(g, 1, false, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  Iter it = iter_view(ctx, L);
+  Iter it = iter_view(ctx->ws, L);
   HIP_TRY(launch_fill_i32(it.bin_cnt, 0, g.nbins, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
   HIP_TRY(launch_prep(g, centres, it, s));
@@ -448,7 +528,7 @@ int sslic_update(sslic_ctx* ctx, const void* image, int ndim, const int64_t* dim
   Layout L = layout(g, 1, false, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  Iter it = iter_view(ctx, L);
+  Iter it = iter_view(ctx->ws, L);
   HIP_TRY(launch_fill_u64(it.acc, 0, g.K * g.F, s));
   HIP_TRY(launch_fill_f64(it.res_acc, 0.0, 2 * kResSlots, s));
   HIP_TRY(launch_fill_i32(it.done, 0, 2, s));
@@ -470,8 +550,8 @@ int sslic_connectivity(sslic_ctx* ctx, int ndim, const int64_t* dims, const int3
   Layout L = layout(g, 1, true, false);
   if ((rc = ensure_ws(ctx, L.total))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  int32_t* nl = nlab_slot(ctx, L);
-  HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx, L, g.N), nl, s));
+  int32_t* nl = nlab_slot(ctx->ws, L);
+  HIP_TRY(launch_connectivity(g, centres, labels, cc_view(ctx->ws, L, g.N), nl, s));
   if (n_labels_dev) HIP_TRY(hipMemcpyAsync(n_labels_dev, nl, 4, hipMemcpyDeviceToDevice, s));
   return read_ints(ctx, s, nl, n_labels_out, nullptr, nullptr);
 }

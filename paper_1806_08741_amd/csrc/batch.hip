@@ -131,7 +131,7 @@ int autotune(sslic_ctx* ctx, const sslic_image_desc& d, const Geo& g, hipStream_
   const size_t o_tile = o_img + al(sizeof(BImg));
   int rc = ensure_ws(ctx, o_tile + al((size_t)ntmax * 4));
   if (rc) return rc;
-  Iter it = iter_view(ctx, L);
+  Iter it = iter_view(ctx->ws, L);
   BImg* dimg = reinterpret_cast<BImg*>(ctx->ws + o_img);
   int32_t* dtile = reinterpret_cast<int32_t*>(ctx->ws + o_tile);
   HIP_TRY(launch_seed(g, d.image, d.centres, s));

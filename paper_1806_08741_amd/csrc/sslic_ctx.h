@@ -62,8 +62,9 @@ struct Layout {
 // persist: room for the distance image kept across iterations (f32 [N])
 Layout layout(const Geo& g, int iterations, bool cc, bool part, bool persist = false);
 int ensure_ws(sslic_ctx* ctx, size_t need);
-Iter iter_view(sslic_ctx* ctx, const Layout& L);
-CCBuf cc_view(sslic_ctx* ctx, const Layout& L, int64_t N);
+// views of a workspace laid out by `layout` at device address `base`
+Iter iter_view(char* base, const Layout& L);
+CCBuf cc_view(char* base, const Layout& L, int64_t N);
 int select_device(sslic_ctx* ctx);
 
 // Brackets the launches of one kernel class with events when profiling

@@ -65,6 +65,8 @@ def lib():
             L.sslic_num_clusters.argtypes = [I, P, P, P, P]
             L.sslic_run.argtypes = [P, P, I, P, I, I, P, D, I, ctypes.POINTER(_Options), P, P, P,
                                     P, P, P]
+            L.sslic_run_static.argtypes = [P, I, P, I, I, P, D, I, ctypes.POINTER(_Options), P,
+                                           P, P, P]
             L.sslic_run_batch.argtypes = [P, ctypes.POINTER(ImageDesc), I,
                                           ctypes.POINTER(_Options), P, P]
             L.sslic_seed.argtypes = [P, P, I, P, I, I, P, P, P]
@@ -75,7 +77,8 @@ def lib():
             L.sslic_connectivity.argtypes = [P, I, P, P, I, P, I64, P, P, P, P]
             L.sslic_mask_contours.argtypes = [P, P, I, P, I, I, P, P, P]
             L.sslic_rgb_to_lab.argtypes = [P, P, I64, P, P]
-            for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_batch",
+            for name in ("sslic_create", "sslic_num_clusters", "sslic_run", "sslic_run_static",
+                         "sslic_run_batch",
                          "sslic_seed", "sslic_grid_labels", "sslic_assign",
                          "sslic_assign_persist", "sslic_update",
                          "sslic_connectivity", "sslic_mask_contours", "sslic_rgb_to_lab"):
@@ -365,3 +368,37 @@ def context(device: int = 0) -> Context:
 
 def run(img: torch.Tensor, S, m, iterations, **kw) -> dict:
     return context(img.device.index or 0).run(img, S, m, iterations, **kw)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # SSLIC_STATIC_SCRATCH_BYTES
+
+
+def run_static(img: torch.Tensor, S, m, iterations, *, tol: float = 0.0,
+               connectivity: bool = True, out: Optional[dict] = None,
+               persist_distance: bool = False) -> dict:
+    """``sslic_run_static``: the whole filter with no device allocation in
+    the library (its workspace is a static device array of 64 MiB per GPU).
+    ``out`` must then hold preallocated ``labels`` (int32 [N]), ``centres``
+    (float64 [K, C + ndim]), ``counts`` (int64 [K]), ``n_labels`` and
+    ``iterations`` (int32 [1] each) on the image's device; without ``out``
+    they are allocated here with torch.  Nothing waits for the stream: the
+    label count and the iterations run stay in those device tensors."""
+    nd, dims, C, dt = _geom(img)
+    dev = img.device
+    o = dict(out or {})
+    if not o:
+        K = num_clusters(dims, S)
+        N = int(img.numel() // C)
+        o = {"labels": torch.empty(N, dtype=torch.int32, device=dev),
+             "centres": torch.empty((K, C + nd), dtype=torch.float64, device=dev),
+             "counts": torch.empty(K, dtype=torch.int64, device=dev),
+             "n_labels": torch.zeros(1, dtype=torch.int32, device=dev),
+             "iterations": torch.zeros(1, dtype=torch.int32, device=dev)}
+    opt = _Options(float(tol), 0 if connectivity else 1, None, None,
+                   o["iterations"].data_ptr(), o["n_labels"].data_ptr(), 0, 0,
+                   1 if persist_distance else 0)
+    with torch.cuda.device(dev):
+        _check(lib().sslic_run_static(_ptr(img), nd, _i64(dims), C, dt, _i32(S), float(m),
+                                      int(iterations), ctypes.byref(opt), _ptr(o["labels"]),
+                                      _ptr(o["centres"]), _ptr(o["counts"]), _stream(dev)))
+    return o

@@ -160,3 +160,23 @@ def test_no_cpu_fallback_without_gpu(lib):
     img = torch.zeros((8, 8, 1), dtype=torch.uint8)
     with pytest.raises(sslic.SslicError, match="GPU"):
         sslic._geom(img)
+
+
+def test_run_static_rejects_large_requests_before_any_device_work(lib):
+    """sslic_run_static refuses a request whose workspace exceeds its static
+    scratch (64 MiB) with SSLIC_ENOMEM before it touches a device, and checks
+    arguments as sslic_run does."""
+    from paper_1806_08741_amd import sslic
+    fake = ctypes.c_void_p(0x1000)
+    o = sslic._Options(0.0, 0, None, None, None, None)
+    dims, S = [3000, 3000], [16, 16]
+    rc = lib.sslic_run_static(fake, 2, sslic._i64(dims), 3, 0, sslic._i32(S), 10.0, 2,
+                              ctypes.byref(o), fake, fake, None, None)
+    assert rc == -2
+    assert "static scratch" in lib.sslic_last_error().decode()
+    rc = lib.sslic_run_static(fake, 2, sslic._i64([64, 64]), 3, 0, sslic._i32(S), 10.0, 0,
+                              ctypes.byref(o), fake, fake, None, None)
+    assert rc == -1
+    rc = lib.sslic_run_static(None, 2, sslic._i64([64, 64]), 3, 0, sslic._i32(S), 10.0, 2,
+                              ctypes.byref(o), fake, fake, None, None)
+    assert rc == -1
