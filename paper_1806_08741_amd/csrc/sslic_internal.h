@@ -107,6 +107,7 @@ struct SweepArgs {
   int nt[kMaxDim];
   int slots;  // 1: per-cluster tile slots; 0: tiles narrower than a window, atomics only
   int table;  // 1: tiles list their meeting centres first (see sweep_table_suits)
+  int fast;   // 1: 2D/3D integer images with few channels take the fast form (sweep.hip)
 };
 // largest cluster count for which a candidate key can carry (k << 6 | lane)
 constexpr int64_t kTableMaxK = (int64_t)1 << 25;

@@ -751,6 +751,595 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fast form for 2D and 3D integer images with up to 3 (3D) or 4 (2D)
+// channels.
+//
+// The workgroup first lists in LDS every centre whose window meets its tile
+// (from the bins within one bin of the tile), in ascending cluster index,
+// with its distance terms relative to the tile's centre o.  With
+//   xs_i = (x_i - o_i) m / S_i,   c_i = c'_i - o_i m / S_i,
+//   D^2 - |xs|^2 = |c|^2 - 2 c . xs + |I - mu|^2,
+// a candidate costs one FMA per axis and two operations per channel; |xs|^2
+// is the same for every centre a voxel compares, so the argmin is that of
+// D^2.  Each wave then sweeps rows of blocks (8 blocks of 8x8 or 4x4x4
+// voxels along axis 0, one voxel per lane): the entries meeting the row are
+// copied to the wave's row list, lane j testing entry j of the list against
+// each block, and the meeting ones are evaluated one at a time with their
+// terms read from LDS as wave-uniform values.  A window that covers only
+// part of the block is applied as a lane mask (the mask of entry j is
+// formed in lane j, a 64-bit bitfield over the block's lanes).  Because the
+// list is in ascending cluster index and the compare is strict, equal
+// distances go to the lowest index.
+//
+// Map step: every voxel adds its packed [1, x - o, I] to its winner's table
+// entry with LDS atomics (no per-lane runs, no hashing: the winner's entry
+// is its table index).  Labels are staged per row in LDS and leave as whole
+// lines.  At the end the table goes to the cluster slots as in the other
+// forms.  Returns false before writing anything when the tile's table would
+// not fit (crowded centres); the caller then runs the general form.
+template <int ND>
+struct Fast;
+template <>
+struct Fast<2> {
+  static constexpr int T[2] = {64, 64};
+  static constexpr int B[2] = {8, 8};
+  static constexpr int kTab = 160;      // table entries
+  static constexpr int kBinRows = 256;  // bin rows (along axis 0) scanned for the table
+  static constexpr int kRep = 2;        // copies of the sums (lanes alternate between them)
+};
+template <>
+struct Fast<3> {
+  static constexpr int T[3] = {32, 32, 32};
+  static constexpr int B[3] = {4, 4, 4};
+  static constexpr int kTab = 320;
+  static constexpr int kBinRows = 256;
+  static constexpr int kRep = 1;
+};
+
+// Where the fast form is used: 3D integer images with 1 to 3 channels.  (It
+// also builds for 2D, but there its per-voxel LDS atomics meet at one
+// address for most lanes of a block -- 2D labels are coherent over a whole
+// 8x8 block -- and the general form's per-lane runs are faster.)
+template <typename T, int ND, int CC>
+constexpr bool fast_ok() {
+  return !std::is_same<T, float>::value && ND == 3 && CC > 0 && 1 + ND + CC <= 7;
+}
+
+template <typename T, int ND, int CC>
+struct FastLds {
+  using SH = Fast<ND>;
+  using PK = TilePack<T, ND, CC, SH>;
+  static constexpr int NW = PK{}.nw;
+  alignas(16) float rec[SH::kTab][8];  // q, -2 c_i (ND), mu_c (C), entry index (int bits)
+  int kk[SH::kTab];        // cluster index of each entry
+  uint32_t tb[ND][SH::kTab];  // window bounds relative to the tile, (lo + 1) | (hi + 1) << 16
+  // packed sums of the tile's voxels per entry, in kRep copies: lane l adds
+  // to copy l mod kRep, so lanes of one label meet at one address less often
+  unsigned long long sum[SH::kRep][SH::kTab][NW];
+  union alignas(16) {
+    float rrec[kWaves][64][8];  // per wave: the entries of the current row
+    int tk[SH::kTab];           // while building: cluster of each unranked entry
+  };
+  union alignas(16) {
+    int lab[kWaves][512];  // per wave: the labels of the current row
+    struct {
+      int pre[SH::kBinRows + 1];  // while building: prefix of the bin-row counts
+      int rstart[SH::kBinRows];   // and the first item of each bin row
+      int wsum[kWaves];
+    } b;
+  };
+  int n;
+};
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return (uint64_t)hi << 32 | lo;
+}
+
+// bits [a, b] of a 64-bit word (empty when b < a); a, b in [0, 63]
+__device__ __forceinline__ uint64_t bit_range(int a, int b) {
+  const uint64_t r = (~0ull >> (63 - b)) & (~0ull << a);
+  return b < a ? 0ull : r;
+}
+
+// bits [a, a + w) of a 32-bit word; w in [0, 8], a in [0, 8]
+__device__ __forceinline__ uint32_t bit_field(int w, int a) {
+  return ((1u << w) - 1u) << a;
+}
+
+// v with bit l cleared, one scalar instruction
+__device__ __forceinline__ uint64_t clear_bit(uint64_t v, int l) {
+  asm("s_bitset0_b64 %0, %1" : "+s"(v) : "s"(l));
+  return v;
+}
+
+template <typename T, int ND, int CC>
+__device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restrict__ img,
+                                                const int32_t* __restrict__ bstart,
+                                                const int32_t* __restrict__ items,
+                                                const float* __restrict__ recs,
+                                                const SweepArgs& a, int iter, int tile,
+                                                FastLds<T, ND, CC>& L) {
+  using SH = Fast<ND>;
+  using PK = TilePack<T, ND, CC, SH>;
+  constexpr PK pk{};
+  constexpr int NW = PK::kFields > 0 ? pk.nw : 1;
+  constexpr int C = CC;
+  const int RS = g.rs;
+  const int F = 1 + ND + C;
+  constexpr int BXN = SH::T[0] / SH::B[0];                 // blocks per row
+  constexpr int NROWS = blocks_per_tile<SH, ND>() / BXN;   // rows per tile
+  static_assert(SH::T[0] * (64 / SH::B[0]) == 512, "a row holds 512 voxels");
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  int to[ND], tc[ND], te[ND];
+  {
+    int r = tile;
+    for (int i = 0; i < ND; ++i) {
+      tc[i] = r % a.nt[i];
+      r /= a.nt[i];
+      to[i] = tc[i] * SH::T[i];
+      te[i] = min(SH::T[i], g.n[i] - to[i]);
+    }
+  }
+
+  // --- the tile's table --------------------------------------------------------
+  int b0[ND], nbr[ND], nrows = 1;
+  for (int i = 0; i < ND; ++i) {
+    b0[i] = max(to[i] / g.S[i] - 1, 0);
+    const int b1 = min((to[i] + te[i] - 1) / g.S[i] + 1, g.nb[i] - 1);
+    nbr[i] = b1 - b0[i] + 1;
+    if (i > 0) nrows *= nbr[i];
+  }
+  if (nrows > SH::kBinRows) return false;
+  if (tid == 0) L.n = 0;
+  {
+    int cnt = 0;
+    if (tid < nrows) {
+      int bl = b0[0] * (int)g.bst[0], rr = tid;
+      for (int i = 1; i < ND; ++i) {
+        bl += (b0[i] + rr % nbr[i]) * (int)g.bst[i];
+        rr /= nbr[i];
+      }
+      const int ja = bstart[bl];
+      cnt = bstart[bl + nbr[0]] - ja;
+      L.b.rstart[tid] = ja;
+    }
+    // inclusive scan of the counts: within each wave, then across waves
+    int v = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(v, d, 64);
+      if (lane >= d) v += u;
+    }
+    if (lane == 63) L.b.wsum[wave] = v;
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < wave; ++w) add += L.b.wsum[w];
+    if (tid < nrows) L.b.pre[tid + 1] = v + add;
+    if (tid == 0) L.b.pre[0] = 0;
+    __syncthreads();
+  }
+  const int nraw = L.b.pre[nrows];
+  if (nraw > 4 * SH::kTab) return false;  // uniform: every thread read the same count
+  for (int i0 = 0; i0 < nraw; i0 += kThreads) {
+    const int i = i0 + tid;
+    bool keep = i < nraw;
+    int k = 0;
+    if (keep) {
+      int lo = 0, hi = nrows;  // the bin row r with pre[r] <= i < pre[r + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.b.pre[mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      k = items[L.b.rstart[lo] + (i - L.b.pre[lo])];
+      const int* irec = reinterpret_cast<const int*>(recs + (int64_t)k * RS);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const int wl = irec[rec_lo(C, ND) + d], wh = irec[rec_hi(C, ND) + d];
+        keep = keep && wl <= to[d] + te[d] - 1 && wh >= to[d];
+      }
+    }
+    const uint64_t m = __ballot(keep);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(&L.n, (int)__popcll(m));
+    base = __builtin_amdgcn_readlane(base, 0);
+    if (keep) {
+      const int p = base + lanes_below(m);
+      if (p < SH::kTab) L.tk[p] = k;
+    }
+  }
+  __syncthreads();
+  const int n = L.n;
+  if (n > SH::kTab) return false;
+  // Coordinates are taken from the tile's centre o_i = to_i + T_i / 2.  q
+  // carries an offset, the smallest power of two above the largest |xs|^2
+  // of the tile, so that the distance the lanes compare, D^2 - |xs|^2 +
+  // offset, is never negative (its bits then order as its values), and
+  // adding it rounds nothing that was exact: equal distances stay equal.
+  double qoff = 1.0;
+  {
+    double mx = 1.0;
+    for (int i = 0; i < ND; ++i) mx += (SH::T[i] / 2 * g.swd[i]) * (SH::T[i] / 2 * g.swd[i]);
+    while (qoff < mx * (1.0 + 1e-6)) qoff *= 2.0;
+  }
+  // rank by cluster index; each entry is written at its rank
+  for (int s = tid; s < n; s += kThreads) {
+    const int k = L.tk[s];
+    int rank = 0;
+    for (int t = 0; t < n; ++t) rank += L.tk[t] < k;
+    const float* rec = recs + (int64_t)k * RS;
+    const int* irec = reinterpret_cast<const int*>(rec);
+    float* R = L.rec[rank];
+    double q = 0.0;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const float cr = (float)((double)rec[C + i] - (double)(to[i] + SH::T[i] / 2) * g.swd[i]);
+      q += (double)cr * (double)cr;
+      R[1 + i] = -2.0f * cr;
+    }
+    R[0] = (float)(q + qoff);
+#pragma unroll
+    for (int c = 0; c < C; ++c) R[1 + ND + c] = rec[c];
+    R[1 + ND + C] = __int_as_float(rank);
+    L.kk[rank] = k;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int lo = min(max(irec[rec_lo(C, ND) + i] - to[i], -1), SH::T[i]);
+      const int hi = min(max(irec[rec_hi(C, ND) + i] - to[i], -1), SH::T[i]);
+      L.tb[i][rank] = (uint32_t)(lo + 1) | (uint32_t)(hi + 1) << 16;
+    }
+#pragma unroll
+    for (int r = 0; r < SH::kRep; ++r)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) L.sum[r][rank][w] = 0;
+  }
+  __syncthreads();
+
+  // --- rows of blocks --------------------------------------------------------
+  int lx[ND];
+  {
+    int r = lane;
+    for (int i = 0; i < ND; ++i) {
+      lx[i] = r % SH::B[i];
+      r /= SH::B[i];
+    }
+  }
+  // the wave's index kept in a vector register, so that addresses into its
+  // row list are formed by one vector add rather than scalar arithmetic
+  const int vwave = (int)(threadIdx.x >> 6);
+
+  // Copies the table entries meeting the box [blo, bhi] (tile-relative) that
+  // sit at positions [c0, c0 + 64) of its list into the wave's list; returns
+  // how many entries meet the box.
+  auto build = [&](const int* blo, const int* bhi, int c0) {
+    int cnt = 0;
+    for (int e0 = 0; e0 < n; e0 += 64) {
+      const int e = e0 + lane;
+      const int ec = min(e, n - 1);
+      bool m = e < n;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const uint32_t w = L.tb[i][ec];
+        const int lo = (int)(w & 0xffffu) - 1, hi = (int)(w >> 16) - 1;
+        m = m & (lo <= bhi[i]) & (hi >= blo[i]);
+      }
+      const uint64_t bal = __ballot(m);
+      const int p = cnt + lanes_below(bal) - c0;
+      if (m && p >= 0 && p < 64) {
+        const float4* src = reinterpret_cast<const float4*>(L.rec[e]);
+        float4* dst = reinterpret_cast<float4*>(L.rrec[wave][p]);
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
+      cnt += (int)__popcll(bal);
+    }
+    __builtin_amdgcn_wave_barrier();
+    return cnt;
+  };
+
+  for (int row = wave; row < NROWS; row += kWaves) {
+    int rlo[ND], rhi[ND];
+    bool rin = true;
+    rlo[0] = 0;
+    rhi[0] = te[0] - 1;
+    {
+      int rr = row;
+      for (int i = 1; i < ND; ++i) {
+        const int nbk = SH::T[i] / SH::B[i];
+        rlo[i] = (rr % nbk) * SH::B[i];
+        rr /= nbk;
+        rhi[i] = min(rlo[i] + SH::B[i], te[i]) - 1;
+        rin = rin && rlo[i] <= rhi[i];
+      }
+    }
+    if (!rin) continue;
+    // this lane's voxel in the row: axes >= 1 fixed, axis 0 per block
+    bool rowok = true;
+    float xs[ND];
+    int64_t vrow = to[0];
+    for (int i = 1; i < ND; ++i) {
+      const int y = rlo[i] + lx[i];
+      rowok = rowok && y <= rhi[i];
+      xs[i] = (float)(y - SH::T[i] / 2) * g.sw[i];
+      vrow += (int64_t)(to[i] + (rowok ? y : rlo[i])) * g.st[i];
+    }
+    const T* prow = img + vrow * C;
+    const T* plane = prow + lx[0] * C;  // this lane's voxel of block 0
+    const int lbase = (ND == 2 ? lx[1] * SH::T[0] : (lx[2] * SH::B[1] + lx[1]) * SH::T[0]);
+
+    // the list (or one 64-entry part of it) the lanes hold: lane j holds
+    // entry j, its window bounds and the row part of its lane mask
+    bool held = false, cyz = false;
+    int lo[ND], hi[ND];
+    uint64_t myz = 0, hm = 0, cym = 0;
+    uint32_t xb0 = 0, xb1 = 0;  // axis-0 coverage of the row by this lane's window
+    auto hold = [&](int nc) {
+      held = lane < nc;
+      const int ej = held ? __float_as_int(L.rrec[wave][lane][1 + ND + C]) : 0;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const uint32_t w = L.tb[i][ej];
+        lo[i] = (int)(w & 0xffffu) - 1;
+        hi[i] = (int)(w >> 16) - 1;
+      }
+      const int a1 = min(max(lo[1] - rlo[1], 0), SH::B[1] - 1);
+      const int b1 = max(min(hi[1] - rlo[1], SH::B[1] - 1), 0);
+      if constexpr (ND == 2) {
+        cyz = (lo[1] <= rlo[1]) & (hi[1] >= rhi[1]);
+        myz = bit_range(a1 * 8, b1 * 8 + 7);
+      } else {
+        const int a2 = min(max(lo[2] - rlo[2], 0), SH::B[2] - 1);
+        const int b2 = max(min(hi[2] - rlo[2], SH::B[2] - 1), 0);
+        cyz = (lo[1] <= rlo[1]) & (hi[1] >= rhi[1]) & (lo[2] <= rlo[2]) & (hi[2] >= rhi[2]);
+        const uint64_t p1 = bit_range(a1 * 4, b1 * 4 + 3);
+        myz = (p1 | p1 << 16 | p1 << 32 | p1 << 48) & bit_range(a2 * 16, b2 * 16 + 15);
+      }
+      hm = __ballot(held);
+      cym = __ballot(cyz);
+      // axis-0 positions of the row (tile-relative) in this lane's window
+      const int xa = max(lo[0], 0), xe = min(hi[0], rhi[0]);
+      if constexpr (ND == 2) {
+        const uint64_t r = bit_range(min(xa, 63), max(xe, 0));
+        xb0 = xa <= xe ? (uint32_t)r : 0u;
+        xb1 = xa <= xe ? (uint32_t)(r >> 32) : 0u;
+      } else {
+        xb0 = xa <= xe ? (uint32_t)bit_range(min(xa, 31), max(xe, 0)) : 0u;
+      }
+    };
+
+    // the held entries that meet block [xlo, xhi] x row, one at a time:
+    // first those whose window covers the block, then those that cover
+    // part of it (masked to the lanes they hold).  The best is one 64-bit
+    // key, the bits of the (non-negative) distance above the entry index,
+    // so the order of evaluation does not matter and equal distances go to
+    // the lowest entry, i.e. the lowest cluster index.
+    auto eval = [&](int xlo, int xhi, const float* Iv, uint32_t& kbh, uint32_t& kbl) {
+      // this lane's window over the block's axis-0 positions, then the lanes
+      // of the block it holds: that range repeated over the block rows,
+      // and the row part
+      constexpr uint32_t kFull = (1u << SH::B[0]) - 1u;
+      uint32_t p;
+      if constexpr (ND == 2) p = ((xlo < 32 ? xb0 : xb1) >> (xlo & 31)) & kFull;
+      else p = (xb0 >> xlo) & kFull;
+      const uint64_t M = hm & __ballot(p != 0u);
+      const uint64_t Cv = M & cym & __ballot(p == kFull);
+      // repeated over 16 lanes with one 24-bit multiply, then over 32
+      p = __umul24(p, ND == 3 ? 0x1111u : 0x0101u);
+      p |= p << 16;
+      const uint64_t pm = ((uint64_t)p << 32 | p) & myz;
+      const float x0 = (float)(xlo + lx[0] - SH::T[0] / 2) * g.sw[0];
+      // entry words: q, -2 c_i (ND), mu_c (C), entry index
+      constexpr int EW = 2 + ND + C;
+      auto load = [&](int l, float* R) {
+        const float* src = L.rrec[vwave][l];
+        if constexpr (EW == 6) {
+          const float4 r0 = *reinterpret_cast<const float4*>(src);
+          const float2 r1 = *reinterpret_cast<const float2*>(src + 4);
+          R[0] = r0.x; R[1] = r0.y; R[2] = r0.z; R[3] = r0.w; R[4] = r1.x; R[5] = r1.y;
+        } else {
+          const float4 r0 = *reinterpret_cast<const float4*>(src);
+          const float4 r1 = *reinterpret_cast<const float4*>(src + 4);
+          const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+          for (int w = 0; w < EW; ++w) R[w] = rr[w];
+        }
+      };
+      auto one = [&](const float* R, auto masked, uint64_t wm) {
+        float D = fmaf(x0, R[1], R[0]);
+#pragma unroll
+        for (int i = 1; i < ND; ++i) D = fmaf(xs[i], R[1 + i], D);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const float t = Iv[c] - R[1 + ND + c];
+          D = fmaf(t, t, D);
+        }
+        const uint32_t khi = __float_as_uint(D), klo = (uint32_t)__float_as_int(R[EW - 1]);
+        bool c = ((uint64_t)khi << 32 | klo) < ((uint64_t)kbh << 32 | kbl);
+        if constexpr (decltype(masked)::value) c = c & __builtin_amdgcn_inverse_ballot_w64(wm);
+        kbh = c ? khi : kbh;
+        kbl = c ? klo : kbl;
+      };
+      // the entries of mask m, one at a time
+      auto walk = [&](uint64_t m, auto masked) {
+        while (m) {
+          const int l = (int)__builtin_ctzll(m);
+          m = clear_bit(m, l);
+          float R[EW];
+          load(l, R);
+          one(R, masked, decltype(masked)::value ? readlane64(pm, l) : 0ull);
+        }
+      };
+      walk(Cv, std::false_type{});
+      walk(M & ~Cv, std::true_type{});
+    };
+
+    // label and sums of this lane's voxel of block bx
+    auto finish = [&](int x, const float* Iv, int e) {
+      int lab;
+      if (e >= 0) {
+        lab = L.kk[e];
+        uint32_t v[PK::kFields];
+        v[0] = 1;
+        v[1] = (uint32_t)x;
+        for (int i = 1; i < ND; ++i) v[1 + i] = (uint32_t)(rlo[i] + lx[i]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[1 + ND + c] = (uint32_t)Iv[c];
+        uint64_t pw[NW];
+        pack_run<PK>(v, pw);
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+          atomicAdd(&L.sum[lane & (SH::kRep - 1)][e][w], (unsigned long long)pw[w]);
+      } else {
+        // no window holds this voxel: its grid cell (first iteration) or
+        // its previous label, summed straight into the accumulators
+        int xa[ND];
+        xa[0] = to[0] + x;
+        for (int i = 1; i < ND; ++i) xa[i] = to[i] + rlo[i] + lx[i];
+        int64_t lin = 0;
+        for (int i = 0; i < ND; ++i) lin += (int64_t)xa[i] * g.st[i];
+        lab = iter == 0 ? grid_label(g, xa, ND) : a.labels[lin];
+        a.accf[lab] = 1;
+        unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)lab * F);
+        atomicAdd(gg, 1ull);
+        for (int i = 0; i < ND; ++i) atomicAdd(gg + 1 + i, (unsigned long long)xa[i]);
+        for (int c = 0; c < C; ++c) atomicAdd(gg + 1 + ND + c, (unsigned long long)Iv[c]);
+      }
+      L.lab[wave][lbase + x] = lab;
+    };
+
+    // one block of the row: its voxels, their best entries, labels and sums
+    auto block = [&](int bx, auto slow) {
+      const int xlo = bx * SH::B[0];
+      const int xhi = min(xlo + SH::B[0] - 1, rhi[0]);
+      const int x = xlo + lx[0];
+      float Iv[C];
+      {
+        // lanes past the image's edge (last block only) read its last voxel
+        const T* px = xlo + SH::B[0] - 1 <= rhi[0] ? plane + xlo * C
+                                                    : prow + (int64_t)min(x, rhi[0]) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) Iv[c] = (float)px[c];
+      }
+      uint32_t kbh = ~0u, kbl = ~0u;  // best key: none yet
+      if constexpr (!decltype(slow)::value) {
+        eval(xlo, xhi, Iv, kbh, kbl);
+      } else {
+        // more than 64 entries meet the row: per block, 64 at a time
+        int bl[ND], bh[ND];
+        bl[0] = xlo;
+        bh[0] = xhi;
+        for (int i = 1; i < ND; ++i) {
+          bl[i] = rlo[i];
+          bh[i] = rhi[i];
+        }
+        for (int c0 = 0;; c0 += 64) {
+          const int bc = build(bl, bh, c0);
+          hold(min(bc - c0, 64));
+          eval(xlo, xhi, Iv, kbh, kbl);
+          if (c0 + 64 >= bc) break;
+        }
+      }
+      if (rowok && x <= rhi[0]) finish(x, Iv, kbh == ~0u ? -1 : (int)kbl);
+    };
+
+    const int nbx = min(BXN, (rhi[0] + SH::B[0]) / SH::B[0]);  // blocks in the image
+    const int cnt = build(rlo, rhi, 0);
+    if (cnt <= 64) {
+      hold(cnt);
+#pragma unroll 1
+      for (int bx = 0; bx < nbx; ++bx) block(bx, std::false_type{});
+    } else {
+#pragma unroll 1
+      for (int bx = 0; bx < nbx; ++bx) block(bx, std::true_type{});
+    }
+    __builtin_amdgcn_wave_barrier();
+    // the row's labels, four per store along axis 0
+    constexpr int Q = SH::T[0] / 4;  // stores per line
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + 64 * h;
+      const int line = q / Q, x = (q % Q) * 4;
+      int yz[ND];
+      bool ok = x <= rhi[0];
+      {
+        int rr = line;
+        for (int i = 1; i < ND; ++i) {
+          yz[i] = rlo[i] + rr % SH::B[i];
+          rr /= SH::B[i];
+          ok = ok && yz[i] <= rhi[i];
+        }
+      }
+      if (!ok) continue;
+      int64_t lin = to[0] + x;
+      for (int i = 1; i < ND; ++i) lin += (int64_t)(to[i] + yz[i]) * g.st[i];
+      const int4 v = *reinterpret_cast<const int4*>(&L.lab[wave][line * SH::T[0] + x]);
+      int32_t* dst = a.labels + lin;
+      if (x + 3 <= rhi[0] && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        *reinterpret_cast<int4*>(dst) = v;
+      } else {
+        dst[0] = v.x;
+        if (x + 1 <= rhi[0]) dst[1] = v.y;
+        if (x + 2 <= rhi[0]) dst[2] = v.z;
+        if (x + 3 <= rhi[0]) dst[3] = v.w;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // --- the tile's sums to their cluster slots -------------------------------
+  constexpr int NS = 1 << ND;
+  for (int s = tid; s < n; s += kThreads) {
+    uint64_t vv[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      vv[w] = 0;
+#pragma unroll
+      for (int r = 0; r < SH::kRep; ++r) vv[w] += L.sum[r][s][w];
+    }
+    const uint64_t nn = PK::field(vv, 0);
+    if (nn == 0) continue;
+    const int k = L.kk[s];
+    uint64_t out[1 + ND + 4];
+    out[0] = nn;
+    for (int i = 0; i < ND; ++i)
+      out[1 + i] = PK::field(vv, 1 + i) + nn * (uint64_t)to[i];
+    for (int c = 0; c < C; ++c) out[1 + ND + c] = PK::field(vv, 1 + ND + c);
+    int q = -1;
+    if (a.slots) {
+      const int* irec = reinterpret_cast<const int*>(a.ctab + (int64_t)k * g.rs);
+      q = 0;
+      for (int i = 0; i < ND; ++i) {
+        const int lo = max(irec[rec_lo(g.C, g.nd) + i], 0), hi = min(irec[rec_hi(g.C, g.nd) + i], g.n[i] - 1);
+        const int t0 = lo / SH::T[i];
+        const int d = tc[i] - t0;
+        const bool meets = to[i] <= hi && to[i] + SH::T[i] - 1 >= lo;
+        if (!meets || d < 0 || d > 1) {
+          q = -1;
+          break;
+        }
+        q |= d << i;
+      }
+    }
+    if (q >= 0) {
+      uint64_t* dst = a.part + ((int64_t)k * NS + q) * (F + 1);
+      for (int f = 0; f < F; ++f) dst[f] = out[f];
+      dst[F] = (uint64_t)(iter + 1);
+    } else {
+      a.accf[k] = 1;
+      unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)k * F);
+      for (int f = 0; f < F; ++f) atomicAdd(gg + f, (unsigned long long)out[f]);
+    }
+  }
+  return true;
+}
+
 // LDS of one workgroup of the sweep
 template <typename T, int ND, int CC, class SH>
 struct SweepLds {
@@ -784,7 +1373,16 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
   const int per = (int)(gridDim.x / 8);
   const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (tile >= a.ntiles) return;
-  if constexpr (ACC) {
+  if constexpr (ACC && fast_ok<T, ND, CC>()) {
+    __shared__ union {
+      FastLds<T, ND, CC> f;
+      SweepLds<T, ND, CC, SH> s;
+    } L;
+    if (a.fast && sweep_tile_fast<T, ND, CC>(g, img, bstart, items, recs, a, a.iter, tile, L.f))
+      return;
+    __syncthreads();  // the fast form's reads of its table are done
+    sweep_tile_acc<T, ND, CC, SH>(g, img, bstart, items, recs, a, a.iter, tile, L.s);
+  } else if constexpr (ACC) {
     __shared__ SweepLds<T, ND, CC, SH> L;
     sweep_tile_acc<T, ND, CC, SH>(g, img, bstart, items, recs, a, a.iter, tile, L);
   } else {
@@ -945,6 +1543,7 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
   a.acc = it.acc;
   a.accf = it.accf;
   a.table = accumulate && sweep_table_suits(g, 0);
+  a.fast = 1;
   return accumulate ? dispatch<true>(g, img, a, s) : dispatch<false>(g, img, a, s);
 }
 

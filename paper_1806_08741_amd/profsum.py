@@ -9,6 +9,11 @@
     python -m paper_1806_08741_amd.profsum copy [--mib M] [--reps R]
         the calibration workload: an elementwise kernel that reads M MiB and
         writes M MiB (``torch.neg(src, out=dst)``), R times
+    python -m paper_1806_08741_amd.profsum valu --kernel K --workload W --units U \
+            --dir DIR [--dir DIR ...] --out FILE
+        instructions per work unit (U units per dispatch, e.g. 64-voxel
+        blocks) and the share of CU cycles the vector and scalar units issue,
+        from SQ counter runs (SQ_INSTS_*, SQ_BUSY_CU_CYCLES)
     python -m paper_1806_08741_amd.profsum traffic --kernel K --workload W \
             --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --mib M --out FILE
         HBM bytes per launch of kernel class K: the FETCH_SIZE and WRITE_SIZE
@@ -159,6 +164,41 @@ def traffic(a) -> dict:
     return rec
 
 
+def valu(a) -> dict:
+    """Per-unit instruction counts and issue shares of one kernel class from
+    one or more SQ counter runs (each counter taken from the run holding it).
+    A CU issues at most one vector and one scalar instruction per cycle
+    (four SIMDs, each every fourth cycle), so instructions per CU over busy
+    cycles per CU is the share of the issue rate used."""
+    pat = KERNELS[a.kernel][0]
+    got = {}
+    for d in a.dir:
+        for k, v in pmc(d, pat).items():
+            for c, x in v.items():
+                if c != "_dispatches":
+                    got.setdefault(c, x)
+    need = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_BUSY_CU_CYCLES")
+    for c in need:
+        if c not in got:
+            raise SystemExit(f"{c} missing under {a.dir}")
+    per = {}
+    for c, name in (("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_SALU", "SALU"), ("SQ_INSTS_SMEM", "SMEM"),
+                    ("SQ_INSTS_LDS", "LDS"), ("SQ_INSTS_BRANCH", "branch")):
+        if c in got:
+            per[name] = round(got[c] / a.units, 1)
+    busy = got["SQ_BUSY_CU_CYCLES"]
+    rec = {"kernel": a.kernel, "workload": a.workload,
+           "source_hash": kernel_source_hash(a.kernel),
+           "valu_busy": round(got["SQ_INSTS_VALU"] / busy, 3),
+           "salu_busy": round(got["SQ_INSTS_SALU"] / busy, 3),
+           "units_per_dispatch": a.units, "per_unit": per}
+    if "SQ_LDS_IDX_ACTIVE" in got:
+        rec["lds_active"] = round(got["SQ_LDS_IDX_ACTIVE"] / busy, 3)
+    if "SQ_LDS_BANK_CONFLICT" in got:
+        rec["lds_bank_conflict"] = round(got["SQ_LDS_BANK_CONFLICT"] / busy, 3)
+    return rec
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="profsum")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -174,6 +214,11 @@ def main(argv=None):
     for k in ("kernel", "workload", "fetch", "write", "copy_fetch", "copy_write", "out"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
     t.add_argument("--mib", type=int, default=1024)
+    v = sub.add_parser("valu")
+    for k in ("kernel", "workload", "out"):
+        v.add_argument("--" + k, required=True)
+    v.add_argument("--units", type=float, required=True)
+    v.add_argument("--dir", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         rows = stats(a.dir)
@@ -187,6 +232,12 @@ def main(argv=None):
             print(f"{k[:64]:64s} n={v['_dispatches']} {cs}")
     elif a.cmd == "copy":
         copy_workload(a.mib, a.reps)
+    elif a.cmd == "valu":
+        rec = valu(a)
+        with open(a.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(rec))
     elif a.cmd == "traffic":
         rec = traffic(a)
         with open(a.out, "w") as fh:
