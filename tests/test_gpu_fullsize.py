@@ -7,7 +7,7 @@ The oracle cannot run these whole in seconds, so the checks are
   * properties that hold at any size: every label valid; the final centres
     are exactly the member means of the final labels (int64 sums on the
     device, one FP64 division, as the update is specified);
-  * connectivity on the full slide labelling, bit-exact against the oracle.
+  * connectivity on the full labellings of both, bit-exact against the oracle.
 """
 import numpy as np
 import pytest
@@ -114,11 +114,17 @@ def test_full_size_run(ctx, name):
     assert len(bad) <= 2, len(bad)
 
 
-def test_full_size_connectivity(ctx):
-    """Connectivity on the full 16384^2 slide labelling equals the oracle's."""
-    w = synth.WORKLOADS["slide-16k"]
-    img = synth.workload_image("slide-16k", "cuda")
+@pytest.mark.parametrize("name", ["slide-16k", "fibsem-1k"])
+def test_full_size_connectivity(ctx, name):
+    """Connectivity on the labelling of a whole workload equals the oracle's,
+    bit for bit: the 16384^2 slide and the 1024^3 volume (there 37% of the
+    voxels are component roots, so the GPU's chains of small components
+    through their predecessors are long and many)."""
+    w = synth.WORKLOADS[name]
+    print(f"[case] connectivity {name} {w.dims}", flush=True)
+    img = synth.workload_image(name, "cuda")
     r = ctx.run(img, list(w.S), w.m, 3, connectivity=False)
+    del img
     labels = r["labels"].clone()
     nl = ctx.connectivity(list(w.dims), list(w.S), r["centres"], w.channels, labels)
     host = r["labels"].cpu().numpy().copy()
