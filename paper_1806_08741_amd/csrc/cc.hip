@@ -82,7 +82,10 @@ struct CCTile<2> {
 };
 template <>
 struct CCTile<3> {
-  static constexpr int L[3] = {4, 4, 4};  // 16^3
+  // 64 x 8 x 8: rows of 256 bytes, so every pass over the tile reads and
+  // writes whole lines, and the faces across axis 0 (each voxel on a line of
+  // its own) hold 64 voxels instead of 256
+  static constexpr int L[3] = {6, 3, 3};
 };
 template <>
 struct CCTile<4> {
