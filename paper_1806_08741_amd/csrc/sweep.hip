@@ -816,6 +816,9 @@ struct FastLds {
   alignas(16) float rec[SH::kTab][8];  // q, -2 c_i (ND), mu_c (C), entry index (int bits)
   int kk[SH::kTab];        // cluster index of each entry
   uint32_t tb[ND][SH::kTab];  // window bounds relative to the tile, (lo + 1) | (hi + 1) << 16
+  // the rows of blocks each entry's window meets: bit b (axis 1) and bit 8 + b
+  // (axis 2) for the b-th block along that axis
+  uint32_t rb[SH::kTab];
   // packed sums of the tile's voxels per entry, in kRep copies: lane l adds
   // to copy l mod kRep, so lanes of one label meet at one address less often
   unsigned long long sum[SH::kRep][SH::kTab][NW];
@@ -1003,6 +1006,19 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       const int hi = min(max(irec[rec_hi(C, ND) + i] - to[i], -1), SH::T[i]);
       L.tb[i][rank] = (uint32_t)(lo + 1) | (uint32_t)(hi + 1) << 16;
     }
+    {
+      uint32_t rb = 0;
+#pragma unroll
+      for (int i = 1; i < ND; ++i) {
+        const int lo = max(irec[rec_lo(C, ND) + i] - to[i], 0);
+        const int hi = min(irec[rec_hi(C, ND) + i] - to[i], SH::T[i] - 1);
+        if (lo <= hi) {
+          const int b0 = lo / SH::B[i], b1 = hi / SH::B[i];
+          rb |= (((1u << (b1 - b0 + 1)) - 1u) << b0) << (8 * (i - 1));
+        }
+      }
+      L.rb[rank] = rb;
+    }
 #pragma unroll
     for (int r = 0; r < SH::kRep; ++r)
 #pragma unroll
@@ -1026,25 +1042,38 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
   // Copies the table entries meeting the box [blo, bhi] (tile-relative) that
   // sit at positions [c0, c0 + 64) of its list into the wave's list; returns
   // how many entries meet the box.
-  auto build = [&](const int* blo, const int* bhi, int c0) {
+  // (a whole row, box = the row: an entry meets it when its window meets the
+  // row's block on every axis >= 1, since every entry meets the tile along
+  // axis 0; a block: the bounds on every axis)
+  auto build = [&](const int* blo, const int* bhi, int c0, auto whole_row) {
     int cnt = 0;
+    uint32_t rbit = 1;
+    if constexpr (decltype(whole_row)::value) {
+      rbit = 1u << (blo[1] / SH::B[1]);
+      if constexpr (ND == 3) rbit |= 1u << (8 + blo[2] / SH::B[2]);
+    }
     for (int e0 = 0; e0 < n; e0 += 64) {
       const int e = e0 + lane;
       const int ec = min(e, n - 1);
       bool m = e < n;
+      if constexpr (decltype(whole_row)::value) {
+        m = m & ((L.rb[ec] & rbit) == rbit);
+      } else {
 #pragma unroll
-      for (int i = 0; i < ND; ++i) {
-        const uint32_t w = L.tb[i][ec];
-        const int lo = (int)(w & 0xffffu) - 1, hi = (int)(w >> 16) - 1;
-        m = m & (lo <= bhi[i]) & (hi >= blo[i]);
+        for (int i = 0; i < ND; ++i) {
+          const uint32_t w = L.tb[i][ec];
+          const int lo = (int)(w & 0xffffu) - 1, hi = (int)(w >> 16) - 1;
+          m = m & (lo <= bhi[i]) & (hi >= blo[i]);
+        }
       }
       const uint64_t bal = __ballot(m);
       const int p = cnt + lanes_below(bal) - c0;
       if (m && p >= 0 && p < 64) {
         const float4* src = reinterpret_cast<const float4*>(L.rec[e]);
+        const float4 a0 = src[0], a1 = src[1];
         float4* dst = reinterpret_cast<float4*>(L.rrec[wave][p]);
-        dst[0] = src[0];
-        dst[1] = src[1];
+        dst[0] = a0;
+        dst[1] = a1;
       }
       cnt += (int)__popcll(bal);
     }
@@ -1079,7 +1108,6 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       vrow += (int64_t)(to[i] + (rowok ? y : rlo[i])) * g.st[i];
     }
     const T* prow = img + vrow * C;
-    const T* plane = prow + lx[0] * C;  // this lane's voxel of block 0
     const int lbase = (ND == 2 ? lx[1] * SH::T[0] : (lx[2] * SH::B[1] + lx[1]) * SH::T[0]);
 
     // the list (or one 64-entry part of it) the lanes hold: lane j holds
@@ -1271,8 +1299,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       float Iv[C];
       {
         // lanes past the image's edge (last block only) read its last voxel
-        const T* px = xlo + SH::B[0] - 1 <= rhi[0] ? plane + xlo * C
-                                                    : prow + (int64_t)min(x, rhi[0]) * C;
+        const T* px = prow + (uint32_t)min(x, rhi[0]) * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) Iv[c] = (float)px[c];
       }
@@ -1289,7 +1316,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
           bh[i] = rhi[i];
         }
         for (int c0 = 0;; c0 += 64) {
-          const int bc = build(bl, bh, c0);
+          const int bc = build(bl, bh, c0, std::false_type{});
           hold(min(bc - c0, 64));
           eval(xlo, xhi, Iv, kbh, kbl);
           if (c0 + 64 >= bc) break;
@@ -1299,7 +1326,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
     };
 
     const int nbx = min(BXN, (rhi[0] + SH::B[0]) / SH::B[0]);  // blocks in the image
-    const int cnt = build(rlo, rhi, 0);
+    const int cnt = build(rlo, rhi, 0, std::true_type{});
     if (cnt <= 64) {
       hold(cnt);
 #pragma unroll 1
