@@ -389,49 +389,66 @@ cc_flatten_kernel(Geo g, CCBuf b) {
 }
 
 // First pass: the component of label k at the rounded centre k, or the first
-// voxel of label k in raster order within floor(S_i / 2) of it.
-__global__ void cc_first_kernel(Geo g, const double* __restrict__ cen,
-                                const int32_t* __restrict__ labels, CCBuf b) {
-  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= g.K) return;
-  const double* row = cen + k * g.row;
-  int p[kMaxDim], lo[kMaxDim], hi[kMaxDim], x[kMaxDim];
+// voxel of label k in raster order within floor(S_i / 2) of it.  Each lane
+// takes one cluster and checks its rounded centre; the wave then reads the
+// window of every cluster whose centre missed, 64 voxels at a time in raster
+// order, and a ballot finds the first of label k.
+__global__ void __launch_bounds__(kThreads)
+cc_first_kernel(Geo g, const double* __restrict__ cen, const int32_t* __restrict__ labels, CCBuf b) {
+  const int lane = threadIdx.x % 64;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = k < g.K;
+  int p[kMaxDim];
   int64_t pl = 0;
-  for (int i = 0; i < g.nd; ++i) {
-    double c = i < g.nd_out ? row[g.C + i] : 0.0;
-    double f = floor(c + 0.5);
-    f = fmin(fmax(f, 0.0), (double)(g.n[i] - 1));
-    p[i] = isfinite(c) ? (int)f : 0;
-    pl += p[i] * g.st[i];
-  }
-  int64_t seed = -1;
-  if (labels[pl] == (int32_t)k) {
-    seed = pl;
-  } else {
+  if (in) {
+    const double* row = cen + k * g.row;
     for (int i = 0; i < g.nd; ++i) {
-      int h = g.S[i] / 2;
-      lo[i] = max(p[i] - h, 0);
-      hi[i] = min(p[i] + h, g.n[i] - 1);
-      x[i] = lo[i];
+      const double c = i < g.nd_out ? row[g.C + i] : 0.0;
+      double f = floor(c + 0.5);
+      f = fmin(fmax(f, 0.0), (double)(g.n[i] - 1));
+      p[i] = isfinite(c) ? (int)f : 0;
+      pl += p[i] * g.st[i];
     }
-    while (true) {
+  }
+  int64_t seed = in && labels[pl] == (int32_t)k ? pl : -1;
+  // the clusters of this wave whose rounded centre holds another label
+  uint64_t miss = __ballot(in && seed < 0);
+  while (miss) {
+    const int j = (int)__builtin_ctzll(miss);
+    miss &= miss - 1;
+    const int kj = __shfl((int)k, j, 64);
+    int lo[kMaxDim], w[kMaxDim];
+    int64_t nwin = 1;
+    for (int i = 0; i < g.nd; ++i) {
+      const int pi = __shfl(i < kMaxDim ? p[i] : 0, j, 64);
+      const int h = g.S[i] / 2;
+      lo[i] = max(pi - h, 0);
+      w[i] = min(pi + h, g.n[i] - 1) - lo[i] + 1;
+      nwin *= w[i];
+    }
+    int64_t found = -1;
+    for (int64_t t0 = 0; t0 < nwin; t0 += 64) {
+      const int64_t t = t0 + lane;
+      bool hit = false;
       int64_t v = 0;
-      for (int i = 0; i < g.nd; ++i) v += x[i] * g.st[i];
-      if (labels[v] == (int32_t)k) {
-        seed = v;
+      if (t < nwin) {
+        int64_t r = t;
+        for (int i = 0; i < g.nd; ++i) {
+          v += (int64_t)(lo[i] + (int)(r % w[i])) * g.st[i];
+          r /= w[i];
+        }
+        hit = labels[v] == kj;
+      }
+      const uint64_t m = __ballot(hit);
+      if (m) {
+        found = (int64_t)__shfl((long long)v, (int)__builtin_ctzll(m), 64);
         break;
       }
-      int i = 0;
-      while (i < g.nd) {
-        if (++x[i] <= hi[i]) break;
-        x[i] = lo[i];
-        ++i;
-      }
-      if (i == g.nd) break;
     }
+    if (lane == j) seed = found;
   }
   if (seed < 0) return;
-  int r = b.parent[seed];
+  const int r = b.parent[seed];
   // a component holds one label, so no other cluster marks it
   const int sz = b.size[r];
   if (sz >= 0 && 4 * (int64_t)sz > g.prodS) b.size[r] = ~sz;
