@@ -27,6 +27,16 @@ constexpr int kScanBlock = kThreads * kScanPer;  // chunk counts one scan block 
 
 inline int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
+// Workgroups are dealt to the 8 XCDs in turn.  This numbers them so that
+// each XCD takes one contiguous eighth of the grid, in order: what
+// neighbouring workgroups share (the rows just before, the roots just
+// behind) is then in that XCD's own L2.  A bijection for any grid size.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int per = nb / 8, rem = nb % 8, x = b % 8;
+  return x * per + min(x, rem) + b / 8;
+}
+
 __device__ __forceinline__ int find_root(const int32_t* parent, int v) {
   int p = parent[v];
   while (p != v) {
@@ -62,7 +72,9 @@ __device__ __forceinline__ void unite_roots(int32_t* parent, int a, int b) {
       a = b;
       b = t;
     }
-    if (atomicCAS(&parent[a], a, b) == a) return;
+    const int old = atomicCAS(&parent[a], a, b);
+    if (old == a) return;
+    a = old;  // a's parent as the atomic saw it: progress even if plain loads lag
   }
 }
 
@@ -133,40 +145,48 @@ __device__ __forceinline__ void unite_local(int* par, int a, int b) {
   }
 }
 
+// Voxel indices fit 32 bits (images hold fewer than 2^31 voxels), so the
+// tile kernels index in int.
+template <int ND>
+struct TileIndex {
+  int o[ND];
+  int st[ND];
+  int base;  // index of the tile origin
+  __device__ TileIndex(const Geo& g, int tile) {
+    tile_origin<ND>(g, tile, o);
+    base = 0;
+    for (int i = 0; i < ND; ++i) {
+      st[i] = (int)g.st[i];
+      base += o[i] * st[i];
+    }
+  }
+  // global index of local voxel j, and whether it lies inside the image
+  __device__ __forceinline__ int at(const Geo& g, int j, bool& in) const {
+    int v = base, sh = 0;
+    in = true;
+    for (int i = 0; i < ND; ++i) {
+      const int x = (j >> sh) & ((1 << CCTile<ND>::L[i]) - 1);
+      sh += CCTile<ND>::L[i];
+      in = in && o[i] + x < g.n[i];
+      v += i == 0 ? x : x * st[i];
+    }
+    return v;
+  }
+};
+
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   __shared__ int s_lab[kPadVox];  // labels, then (once unions are done) local sizes
   __shared__ int s_par[kPadVox];
   int* s_size = s_lab;
-  int o[ND];
-  tile_origin<ND>(g, blockIdx.x, o);
-  auto local_coords = [&](int j, int* x) {
-    int sh = 0;
-    for (int i = 0; i < ND; ++i) {
-      x[i] = (j >> sh) & ((1 << CCTile<ND>::L[i]) - 1);
-      sh += CCTile<ND>::L[i];
-    }
-  };
-  auto global_index = [&](const int* x, bool& in) {
-    int64_t v = 0;
-    in = true;
-    for (int i = 0; i < ND; ++i) {
-      const int gx = o[i] + x[i];
-      in = in && gx < g.n[i];
-      v += (int64_t)gx * g.st[i];
-    }
-    return v;
-  };
+  const TileIndex<ND> ti(g, blockIdx.x);
   {
     int lab[kSeg];  // all of this thread's loads in flight at once
 #pragma unroll
     for (int q = 0; q < kSeg; ++q) {
-      const int j = threadIdx.x + q * kThreads;
-      int x[ND];
-      local_coords(j, x);
       bool in;
-      const int64_t v = global_index(x, in);
+      const int v = ti.at(g, threadIdx.x + q * kThreads, in);
       lab[q] = in ? labels[v] : -1;
     }
 #pragma unroll
@@ -184,25 +204,33 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   int own[kSeg];
 #pragma unroll
   for (int q = 0; q < kSeg; ++q) own[q] = s_lab[pd(j0 + q)];
+  uint32_t starts = 1;  // bit q: a run begins at j0 + q
   {
     int start = j0;
 #pragma unroll
     for (int q = 1; q < kSeg; ++q) {
-      if (own[q] != own[q - 1]) start = j0 + q;
+      if (own[q] != own[q - 1]) {
+        start = j0 + q;
+        starts |= 1u << q;
+      }
       s_par[pd(j0 + q)] = start;
     }
   }
   __syncthreads();
   // ... then runs are united with the voxel before the segment and with the
-  // rows below, once where an overlap of two runs begins
+  // rows below, once where an overlap of two runs begins.  The pairs to unite
+  // are collected first (bit 16 (i - 1) + q: voxel q and its neighbour below
+  // along axis i; bit 63: the first voxel and the one before the segment) and
+  // then taken one by one, so the wave loops as often as its busiest lane
+  // has pairs, not once per voxel that any lane unites.
   {
-    int x0[ND];
-    local_coords(j0, x0);
-    if (x0[0] > 0 && own[0] >= 0 && own[0] == s_lab[pd(j0 - 1)]) unite_local(s_par, j0 - 1, j0);
+    uint64_t todo = 0;
     int sh = CCTile<ND>::L[0];
+    const int x0 = j0 & ((1 << sh) - 1);
+    if (x0 > 0 && own[0] >= 0 && own[0] == s_lab[pd(j0 - 1)]) todo |= 1ull << 63;
 #pragma unroll
     for (int i = 1; i < ND; ++i) {
-      if (x0[i] > 0) {
+      if (((j0 >> sh) & ((1 << CCTile<ND>::L[i]) - 1)) > 0) {
         const int d = 1 << sh;
         int below[kSeg];
 #pragma unroll
@@ -212,42 +240,64 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
           const int l = own[q];
           if (l < 0 || below[q] != l) continue;
           if (q > 0 && own[q - 1] == l && below[q - 1] == l) continue;  // same pair of runs
-          unite_local(s_par, j0 + q - d, j0 + q);
+          todo |= 1ull << (16 * (i - 1) + q);
         }
       }
       sh += CCTile<ND>::L[i];
     }
-  }
-  __syncthreads();
-  {  // every voxel to its local root (first steps read together)
-    int p[kSeg];
+    while (todo) {
+      const int t = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      int a, c;
+      if (t == 63) {
+        a = j0 - 1;
+        c = j0;
+      } else {
+        const int i = t >> 4;  // axis - 1
+        int dsh = CCTile<ND>::L[0];
 #pragma unroll
-    for (int q = 0; q < kSeg; ++q) p[q] = s_par[pd(threadIdx.x + q * kThreads)];
-#pragma unroll
-    for (int q = 0; q < kSeg; ++q) {
-      const int j = threadIdx.x + q * kThreads;
-      if (p[q] != j) s_par[pd(j)] = find_local(s_par, p[q]);
+        for (int k = 1; k < ND - 1; ++k) dsh += k <= i ? CCTile<ND>::L[k] : 0;
+        c = j0 + (t & 15);
+        a = c - (1 << dsh);
+      }
+      unite_local(s_par, a, c);
     }
   }
   __syncthreads();
-  // labels are no longer needed: voxels outside the image get parent -1 and
-  // the label words become the size counters
-  for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
-    if (s_lab[pd(j)] < 0) s_par[pd(j)] = -1;
-    s_size[pd(j)] = 0;
+  int rt[kSeg];  // local root of each voxel of the segment
+  {
+    // each run's first voxel finds its root (one find per run, taken one by
+    // one as above); the other voxels of the run take it from there
+    uint32_t m = starts;
+    while (m) {
+      const int q = (int)__builtin_ctz(m);
+      m &= m - 1;
+      s_par[pd(j0 + q)] = find_local(s_par, j0 + q);
+    }
+    int cur = 0;
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      if (starts & (1u << q)) cur = s_par[pd(j0 + q)];
+      rt[q] = own[q] < 0 ? -1 : cur;  // voxels outside the image: -1
+    }
   }
   __syncthreads();
-  {  // sizes: each thread counts its 16 consecutive voxels, one atomic per run
-    int r[kSeg];
+  // labels are no longer needed: the label words become the size counters,
+  // and every voxel's parent its local root
 #pragma unroll
-    for (int q = 0; q < kSeg; ++q) r[q] = s_par[pd(j0 + q)];
+  for (int q = 0; q < kSeg; ++q) {
+    s_par[pd(j0 + q)] = rt[q];
+    s_size[pd(j0 + q)] = 0;
+  }
+  __syncthreads();
+  {  // sizes: one atomic per run of equal roots
     int cur = -1, n = 0;
 #pragma unroll
     for (int q = 0; q < kSeg; ++q) {
-      if (r[q] < 0) continue;
-      if (r[q] != cur) {
+      if (rt[q] < 0) continue;
+      if (rt[q] != cur) {
         if (n) atomicAdd(&s_size[pd(cur)], n);
-        cur = r[q];
+        cur = rt[q];
         n = 0;
       }
       ++n;
@@ -255,57 +305,99 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     if (n) atomicAdd(&s_size[pd(cur)], n);
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < kTileVox; j += kThreads) {
-    if (s_par[pd(j)] < 0) continue;
-    int x[ND], xr[ND];
-    local_coords(j, x);
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    const int r = s_par[pd(j)];
+    if (r < 0) continue;
     bool in;
-    const int64_t v = global_index(x, in);
-    local_coords(s_par[pd(j)], xr);
-    const int64_t r = global_index(xr, in);
-    b.parent[v] = (int32_t)r;
+    const int v = ti.at(g, j, in);
+    b.parent[v] = ti.at(g, r, in);
     b.size[v] = s_size[pd(j)];  // non-zero exactly at local roots
   }
 }
 
 // Unions across the low face x_i = o_i of every tile, on the global parents.
-// The face is walked with the first other axis fastest, one voxel per lane;
+// The faces of a tile are numbered one after the other (a wave stays within
+// one face) and walked with the first other axis fastest, one voxel per lane;
 // a pair equal to the pair one step before it along that axis (same label
 // on both sides) is already joined through it, since each side's pair of
 // voxels lies in one local component, so only the first pair of each such
-// overlap unites.
+// overlap unites.  All label and parent loads of a thread are issued before
+// its unions, which are then taken one by one.
+template <int ND>
+struct Faces {
+  static constexpr int nf(int i) { return kTileVox >> CCTile<ND>::L[i]; }
+  static constexpr int total() {
+    int t = 0;
+    for (int i = 0; i < ND; ++i) t += nf(i);
+    return t;
+  }
+  static constexpr int kItems = (total() + kThreads - 1) / kThreads;
+};
+
 template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
-  int o[ND];
-  tile_origin<ND>(g, blockIdx.x, o);
-  for (int i = 0; i < ND; ++i) {
-    if (o[i] == 0) continue;
-    const int nf = kTileVox >> CCTile<ND>::L[i];
-    const int ea = 1 << CCTile<ND>::L[i == 0 ? 1 : 0];  // extent of the fastest face axis
-    for (int f0 = 0; f0 < nf; f0 += kThreads) {
-      const int f = f0 + (int)threadIdx.x;
-      int r = f;
-      int64_t v = 0;
-      bool in = f < nf;
-      for (int a = 0; a < ND; ++a) {
-        int xa;
-        if (a == i) {
-          xa = o[a];
-        } else {
-          xa = o[a] + (r & ((1 << CCTile<ND>::L[a]) - 1));
-          r >>= CCTile<ND>::L[a];
-        }
-        in = in && xa < g.n[a];
-        v += (int64_t)xa * g.st[a];
+  const TileIndex<ND> ti(g, blockIdx.x);
+  constexpr int K = Faces<ND>::kItems;
+  int v[K], u[K], lv[K], lu[K], ax[K], f[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int F = (int)threadIdx.x + k * kThreads;
+    int i = 0;
+    while (i < ND - 1 && F >= Faces<ND>::nf(i)) F -= Faces<ND>::nf(i++);
+    bool in = F < Faces<ND>::nf(i);
+    int r = F, vi = ti.base, du = 0;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      int xa = 0;
+      if (a != i) {
+        xa = r & ((1 << CCTile<ND>::L[a]) - 1);
+        r >>= CCTile<ND>::L[a];
+      } else {
+        in = in && ti.o[a] > 0;
+        du = a == 0 ? 1 : ti.st[a];
       }
-      const int64_t u = v - g.st[i];
-      const int lv = in ? labels[v] : -1, lu = in ? labels[u] : -2;
-      // the pair one step before along the fastest face axis (the lane before)
-      const int pv = __shfl_up(lv, 1, 64), pu = __shfl_up(lu, 1, 64);
-      const bool first = f % ea == 0 || pv != lv || pu != lu;
-      if (in && lu == lv && first) unite_roots(b.parent, b.parent[u], b.parent[v]);
+      in = in && ti.o[a] + xa < g.n[a];
+      vi += a == 0 ? xa : xa * ti.st[a];
     }
+    ax[k] = in ? i : -1;
+    f[k] = F;
+    v[k] = vi;
+    u[k] = vi - du;
+    lv[k] = in ? labels[vi] : -1;
+    lu[k] = in ? labels[vi - du] : -2;
+  }
+  uint32_t need = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // the pair one step before along the fastest face axis (the lane before)
+    const int pv = __shfl_up(lv[k], 1, 64), pu = __shfl_up(lu[k], 1, 64);
+    const int i = ax[k];
+    const int ea = 1 << CCTile<ND>::L[i == 0 ? 1 : 0];  // extent of the fastest face axis
+    const bool first = f[k] % ea == 0 || pv != lv[k] || pu != lu[k];
+    if (i >= 0 && lu[k] == lv[k] && first) need |= 1u << k;
+  }
+  int pa[K], pb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool n = need & (1u << k);
+    pa[k] = n ? b.parent[u[k]] : 0;
+    pb[k] = n ? b.parent[v[k]] : 0;
+  }
+  while (need) {
+    const int k = (int)__builtin_ctz(need);
+    need &= need - 1;
+    int a = pa[0], c = pb[0];
+#pragma unroll
+    for (int k2 = 1; k2 < K; ++k2) {
+      if (k == k2) {
+        a = pa[k2];
+        c = pb[k2];
+      }
+    }
+    unite_roots(b.parent, a, c);
   }
 }
 
@@ -317,74 +409,70 @@ template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_flatten_kernel(Geo g, CCBuf b) {
   __shared__ int s_root[kTileVox];  // global root, at the local roots' entries
-  int o[ND];
-  tile_origin<ND>(g, blockIdx.x, o);
-  int64_t base = 0;
+  const TileIndex<ND> ti(g, xcd_block());
   float inv[ND];
-  for (int i = 0; i < ND; ++i) {
-    base += (int64_t)o[i] * g.st[i];
-    inv[i] = 1.0f / (float)g.st[i];
+  for (int i = 0; i < ND; ++i) inv[i] = 1.0f / (float)ti.st[i];
+  int sz[kSeg], par[kSeg], vq[kSeg];  // all of this thread's loads in flight at once
+  uint32_t inm = 0, lr = 0;           // bit q: inside the image / a local root
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    bool in;
+    vq[q] = ti.at(g, threadIdx.x + q * kThreads, in);
+    sz[q] = in ? b.size[vq[q]] : 0;
+    par[q] = in ? b.parent[vq[q]] : -1;
+    inm |= in ? 1u << q : 0u;
   }
-  auto voxel = [&](int j, int64_t& v) {
-    int sh = 0;
-    bool in = true;
-    v = 0;
-    for (int i = 0; i < ND; ++i) {
-      const int gx = o[i] + ((j >> sh) & ((1 << CCTile<ND>::L[i]) - 1));
-      sh += CCTile<ND>::L[i];
-      in = in && gx < g.n[i];
-      v += (int64_t)gx * g.st[i];
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) lr |= sz[q] > 0 ? 1u << q : 0u;
+  {  // the local roots, one by one (the wave loops as often as its busiest lane)
+    uint32_t m = lr;
+    while (m) {
+      const int q = (int)__builtin_ctz(m);
+      m &= m - 1;
+      int v = vq[0], p = par[0], s = sz[0];
+#pragma unroll
+      for (int q2 = 1; q2 < kSeg; ++q2) {
+        if (q == q2) {
+          v = vq[q2];
+          p = par[q2];
+          s = sz[q2];
+        }
+      }
+      const int r = p == v ? v : find_root(b.parent, v);
+      s_root[threadIdx.x + q * kThreads] = r;
+      if (r != v) atomicAdd(&b.size[r], s);  // a local root joins its global root
     }
-    return in;
-  };
-  int sz[kSeg], par[kSeg];  // all of this thread's loads in flight at once
-#pragma unroll
-  for (int q = 0; q < kSeg; ++q) {
-    int64_t v;
-    const bool in = voxel(threadIdx.x + q * kThreads, v);
-    sz[q] = in ? b.size[v] : 0;
-    par[q] = in ? b.parent[v] : -1;
-  }
-#pragma unroll
-  for (int q = 0; q < kSeg; ++q) {
-    if (sz[q] <= 0) continue;
-    const int j = threadIdx.x + q * kThreads;
-    int64_t v;
-    voxel(j, v);
-    const int r = par[q] == (int)v ? (int)v : find_root(b.parent, (int)v);
-    s_root[j] = r;
-    if (r != (int)v) atomicAdd(&b.size[r], sz[q]);  // a local root joins its global root
-    par[q] = -1;
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kSeg; ++q) {
+    if (!(inm & (1u << q))) continue;
     const int j = threadIdx.x + q * kThreads;
-    int64_t v;
-    if (!voxel(j, v)) continue;
     int r;
-    if (par[q] < 0) {
-      r = s_root[j];  // a local root
+    if (lr & (1u << q)) {
+      r = s_root[j];
     } else {
       // the local root's tile-local index from its offset to the tile origin
-      int64_t d = (int64_t)par[q] - base;
+      // (each quotient is below the tile extent, so the FP32 estimate is off
+      // by at most one)
+      int d = par[q] - ti.base;
       int lj = 0, sh = 0;
       int xq[ND];
       for (int i = ND - 1; i >= 1; --i) {
         int qi = (int)((float)d * inv[i]);
-        if ((int64_t)qi * g.st[i] > d) --qi;
-        else if ((int64_t)(qi + 1) * g.st[i] <= d) ++qi;
+        if ((int64_t)qi * ti.st[i] > d) --qi;
+        else if ((int64_t)(qi + 1) * ti.st[i] <= d) ++qi;
         xq[i] = qi;
-        d -= (int64_t)qi * g.st[i];
+        d -= qi * ti.st[i];
       }
-      xq[0] = (int)d;
+      xq[0] = d;
       for (int i = 0; i < ND; ++i) {
         lj |= xq[i] << sh;
         sh += CCTile<ND>::L[i];
       }
       r = s_root[lj];
     }
-    b.parent[v] = r;
+    b.parent[vq[q]] = r;
   }
 }
 
@@ -458,7 +546,7 @@ cc_first_kernel(Geo g, const double* __restrict__ cen, const int32_t* __restrict
 // Wave w of block x ranks chunk c = 4x + w: voxels [1024 c, 1024 c + 1024)
 // as 16 coalesced rows of 64, in raster order.
 __device__ __forceinline__ int64_t wave_chunk() {
-  return (int64_t)blockIdx.x * kWaves + threadIdx.x / 64;
+  return (int64_t)xcd_block() * kWaves + threadIdx.x / 64;
 }
 
 constexpr int kRows = kChunk / 64;
@@ -620,37 +708,55 @@ cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b, int64_
 
 // Small roots take the label their link leads to (most links end at once:
 // the neighbour before a small root usually lies in a large or final
-// component).  Lanes take consecutive roots, and each thread follows four
-// chains at a time.  Every root's entry is written once, by its own thread,
-// from link to label, so any entry read on the way is valid.
+// component).  The root list is cut into units of 1024 consecutive roots,
+// and each XCD walks one contiguous eighth of the units in order: a link
+// leads a few rows back, to roots its own XCD has just resolved.  Each
+// thread follows four chains 256 roots apart.  Every root's entry is written
+// once, by its own thread, from link to label, so any entry read on the way
+// is valid.  The grid is a multiple of 8 workgroups.
 __global__ void __launch_bounds__(kThreads) cc_resolve_kernel(CCBuf b) {
   constexpr int U = 4;
   const int n = *b.nroots;
-  const int stride = gridDim.x * blockDim.x;
-  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+  const int W = (n + kThreads * U - 1) / (kThreads * U);
+  const int x = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
+  const int ue = (int)((int64_t)W * (x + 1) / 8);
+  for (int u = (int)((int64_t)W * x / 8) + (int)(blockIdx.x / 8); u < ue; u += per) {
+    const int i0 = u * kThreads * U + (int)threadIdx.x;
     int v[U], lab[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = i0 + u * stride < n ? b.roots[i0 + u * stride] : -1;
+    for (int k = 0; k < U; ++k) v[k] = i0 + k * kThreads < n ? b.roots[i0 + k * kThreads] : -1;
 #pragma unroll
-    for (int u = 0; u < U; ++u) lab[u] = v[u] >= 0 ? b.newlab[v[u]] : 0;
+    for (int k = 0; k < U; ++k) lab[k] = v[k] >= 0 ? b.newlab[v[k]] : 0;
     int w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) w[u] = lab[u] < 0 ? b.newlab[-lab[u] - 1] : 0;
+    for (int k = 0; k < U; ++k) w[k] = lab[k] < 0 ? b.newlab[-lab[k] - 1] : 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (lab[u] >= 0) continue;
-      int lu = w[u];
-      while (lu < 0) lu = b.newlab[-lu - 1];
-      b.newlab[v[u]] = lu;
+    for (int k = 0; k < U; ++k) {
+      if (lab[k] >= 0) continue;
+      int lk = w[k];
+      while (lk < 0) lk = b.newlab[-lk - 1];
+      b.newlab[v[k]] = lk;
     }
   }
 }
 
-// Every voxel takes the label of its component's root.
+// Every voxel takes the label of its component's root; four voxels 256
+// apart per thread, their gathers in flight together.
+constexpr int kRelabelPer = 4;
 __global__ void __launch_bounds__(kThreads)
 cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, int32_t* n_labels) {
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v < g.N) labels[v] = b.newlab[b.parent[v]];
+  const int64_t v0 = (int64_t)xcd_block() * (kThreads * kRelabelPer) + threadIdx.x;
+  int p[kRelabelPer];
+#pragma unroll
+  for (int k = 0; k < kRelabelPer; ++k) {
+    const int64_t v = v0 + k * kThreads;
+    p[k] = v < g.N ? b.parent[v] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kRelabelPer; ++k) {
+    const int64_t v = v0 + k * kThreads;
+    if (v < g.N) labels[v] = b.newlab[p[k]];
+  }
   if (n_labels && blockIdx.x == 0 && threadIdx.x == 0) *n_labels = (int32_t)(g.K + *b.total);
 }
 
@@ -689,8 +795,10 @@ hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
   cc_scan_blocks_kernel<<<1, kThreads, 0, s>>>(b, nsb);
   cc_scan_add_kernel<<<blocks_for(nchunks), kThreads, 0, s>>>(b, nchunks);
   cc_root_labels_kernel<<<nwg, kThreads, 0, s>>>(g, labels, b, nchunks);
-  cc_resolve_kernel<<<(int)std::min<int64_t>(blocks_for(g.N), 1 << 16), kThreads, 0, s>>>(b);
-  cc_relabel_kernel<<<blocks_for(g.N), kThreads, 0, s>>>(g, labels, b, n_labels_dev);
+  const int64_t units = (g.N + 4 * kThreads - 1) / (4 * kThreads);
+  cc_resolve_kernel<<<(int)((std::min<int64_t>(units, 1 << 16) + 7) / 8 * 8), kThreads, 0, s>>>(b);
+  cc_relabel_kernel<<<(int)((g.N + kThreads * kRelabelPer - 1) / (kThreads * kRelabelPer)), kThreads,
+                      0, s>>>(g, labels, b, n_labels_dev);
   return hipGetLastError();
 }
 
