@@ -752,8 +752,7 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
-// Fast form for 2D and 3D integer images with up to 3 (3D) or 4 (2D)
-// channels.
+// Fast form for 3D integer images with up to 3 channels.
 //
 // The workgroup first lists in LDS every centre whose window meets its tile
 // (from the bins within one bin of the tile), in ascending cluster index,
@@ -762,15 +761,17 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
 //   D^2 - |xs|^2 = |c|^2 - 2 c . xs + |I - mu|^2,
 // a candidate costs one FMA per axis and two operations per channel; |xs|^2
 // is the same for every centre a voxel compares, so the argmin is that of
-// D^2.  Each wave then sweeps rows of blocks (8 blocks of 8x8 or 4x4x4
-// voxels along axis 0, one voxel per lane): the entries meeting the row are
-// copied to the wave's row list, lane j testing entry j of the list against
-// each block, and the meeting ones are evaluated one at a time with their
-// terms read from LDS as wave-uniform values.  A window that covers only
-// part of the block is applied as a lane mask (the mask of entry j is
-// formed in lane j, a 64-bit bitfield over the block's lanes).  Because the
-// list is in ascending cluster index and the compare is strict, equal
-// distances go to the lowest index.
+// D^2.  Each wave then sweeps rows of blocks (8 blocks of 4x4x4 voxels
+// along axis 0, one voxel per lane, each lane holding its 8 voxels of the
+// row): the entries meeting the row are copied to the wave's row list, and
+// the wave walks that list once, entry by entry with its terms read from
+// LDS as wave-uniform values.  An entry's terms along axes 1 and 2 are
+// summed once for the row; each block its window meets then costs one FMA
+// for axis 0, two operations per channel, a compare and two selects.  A
+// window that covers only part of a block is applied as a lane mask (formed
+// in scalar registers from the entry's coverage bits).  Because the list is
+// in ascending cluster index and the compare is strict, equal distances go
+// to the lowest index.
 //
 // Map step: every voxel adds its packed [1, x - o, I] to its winner's table
 // entry with LDS atomics (no per-lane runs, no hashing: the winner's entry
@@ -781,28 +782,18 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
 template <int ND>
 struct Fast;
 template <>
-struct Fast<2> {
-  static constexpr int T[2] = {64, 64};
-  static constexpr int B[2] = {8, 8};
-  static constexpr int kTab = 160;      // table entries
-  static constexpr int kBinRows = 256;  // bin rows (along axis 0) scanned for the table
-  static constexpr int kRep = 1;        // copies of the sums (lanes alternate between them)
-  static constexpr bool kRuns = true;   // sums added in runs along the row (see flush)
-};
-template <>
 struct Fast<3> {
   static constexpr int T[3] = {32, 32, 32};
   static constexpr int B[3] = {4, 4, 4};
-  static constexpr int kTab = 320;
-  static constexpr int kBinRows = 256;
-  static constexpr int kRep = 1;
-  static constexpr bool kRuns = false;
+  static constexpr int kTab = 320;      // table entries
+  static constexpr int kBinRows = 256;  // bin rows (along axis 0) scanned for the table
+  static constexpr int kRep = 1;        // copies of the sums (lanes alternate between them)
 };
 
-// Where the fast form is used: 3D integer images with 1 to 3 channels.  (It
-// builds for 2D too, with sums added in runs along the row, but there the
-// general form, whose candidates are scalar loads rather than LDS reads,
-// measured faster: 1.40 against 1.54-1.57 ms on the 16384^2 slide.)
+// Where the fast form is used: 3D integer images with 1 to 3 channels.  (An
+// earlier 2D variant of it measured slower than the general form, whose
+// candidates are scalar loads rather than LDS reads: 1.54-1.57 against
+// 1.40 ms on the 16384^2 slide.)
 template <typename T, int ND, int CC>
 constexpr bool fast_ok() {
   return !std::is_same<T, float>::value && ND == 3 && CC > 0 && 1 + ND + CC <= 7;
@@ -858,13 +849,6 @@ __device__ __forceinline__ uint32_t bit_field(int w, int a) {
 __device__ __forceinline__ uint64_t clear_bit(uint64_t v, int l) {
   asm("s_bitset0_b64 %0, %1" : "+s"(v) : "s"(l));
   return v;
-}
-
-// index of the lowest set bit of v, -1 when v is 0 (one scalar instruction)
-__device__ __forceinline__ int first_bit(uint64_t v) {
-  int r;
-  asm("s_ff1_i32_b64 %0, %1" : "=s"(r) : "s"(v));
-  return r;
 }
 
 template <typename T, int ND, int CC>
@@ -1110,12 +1094,13 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
     const T* prow = img + vrow * C;
     const int lbase = (ND == 2 ? lx[1] * SH::T[0] : (lx[2] * SH::B[1] + lx[1]) * SH::T[0]);
 
-    // the list (or one 64-entry part of it) the lanes hold: lane j holds
-    // entry j, its window bounds and the row part of its lane mask
-    bool held = false, cyz = false;
+    // The list (or one 64-entry part of it) the lanes hold: lane j holds
+    // entry j, its window bounds, the part of its lane mask along axes 1 and
+    // 2, and its coverage of the row's axis-0 positions.
+    bool held = false;
     int lo[ND], hi[ND];
-    uint64_t myz = 0, hm = 0, cym = 0;
-    uint32_t xb0 = 0, xb1 = 0;  // axis-0 coverage of the row by this lane's window
+    uint64_t myz = 0, hm = 0;
+    uint32_t xb0 = 0;  // axis-0 positions of the row (tile-relative) in the window
     auto hold = [&](int nc) {
       held = lane < nc;
       const int ej = held ? __float_as_int(L.rrec[wave][lane][1 + ND + C]) : 0;
@@ -1127,215 +1112,143 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       }
       const int a1 = min(max(lo[1] - rlo[1], 0), SH::B[1] - 1);
       const int b1 = max(min(hi[1] - rlo[1], SH::B[1] - 1), 0);
-      if constexpr (ND == 2) {
-        cyz = (lo[1] <= rlo[1]) & (hi[1] >= rhi[1]);
-        myz = bit_range(a1 * 8, b1 * 8 + 7);
-      } else {
-        const int a2 = min(max(lo[2] - rlo[2], 0), SH::B[2] - 1);
-        const int b2 = max(min(hi[2] - rlo[2], SH::B[2] - 1), 0);
-        cyz = (lo[1] <= rlo[1]) & (hi[1] >= rhi[1]) & (lo[2] <= rlo[2]) & (hi[2] >= rhi[2]);
-        const uint64_t p1 = bit_range(a1 * 4, b1 * 4 + 3);
-        myz = (p1 | p1 << 16 | p1 << 32 | p1 << 48) & bit_range(a2 * 16, b2 * 16 + 15);
-      }
+      const int a2 = min(max(lo[2] - rlo[2], 0), SH::B[2] - 1);
+      const int b2 = max(min(hi[2] - rlo[2], SH::B[2] - 1), 0);
+      const uint64_t p1 = bit_range(a1 * 4, b1 * 4 + 3);
+      myz = (p1 | p1 << 16 | p1 << 32 | p1 << 48) & bit_range(a2 * 16, b2 * 16 + 15);
       hm = __ballot(held);
-      cym = __ballot(cyz);
-      // axis-0 positions of the row (tile-relative) in this lane's window
       const int xa = max(lo[0], 0), xe = min(hi[0], rhi[0]);
-      if constexpr (ND == 2) {
-        const uint64_t r = bit_range(min(xa, 63), max(xe, 0));
-        xb0 = xa <= xe ? (uint32_t)r : 0u;
-        xb1 = xa <= xe ? (uint32_t)(r >> 32) : 0u;
-      } else {
-        xb0 = xa <= xe ? (uint32_t)bit_range(min(xa, 31), max(xe, 0)) : 0u;
-      }
+      xb0 = xa <= xe ? (uint32_t)bit_range(min(xa, 31), max(xe, 0)) : 0u;
     };
 
-    // the held entries that meet block [xlo, xhi] x row, one at a time:
-    // first those whose window covers the block, then those that cover
-    // part of it (masked to the lanes they hold).  The best is one 64-bit
-    // key, the bits of the (non-negative) distance above the entry index,
-    // so the order of evaluation does not matter and equal distances go to
-    // the lowest entry, i.e. the lowest cluster index.
-    auto eval = [&](int xlo, int xhi, const float* Iv, uint32_t& kbh, uint32_t& kbl) {
-      // this lane's window over the block's axis-0 positions, then the lanes
-      // of the block it holds: that range repeated over the block rows,
-      // and the row part
-      constexpr uint32_t kFull = (1u << SH::B[0]) - 1u;
-      uint32_t p;
-      if constexpr (ND == 2) p = ((xlo < 32 ? xb0 : xb1) >> (xlo & 31)) & kFull;
-      else p = (xb0 >> xlo) & kFull;
-      const uint64_t M = hm & __ballot(p != 0u);
-      const uint64_t Cv = M & cym & __ballot(p == kFull);
-      // repeated over 16 lanes with one 24-bit multiply, then over 32
-      p = __umul24(p, ND == 3 ? 0x1111u : 0x0101u);
-      p |= p << 16;
-      const uint64_t pm = ((uint64_t)p << 32 | p) & myz;
-      const float x0 = (float)(xlo + lx[0] - SH::T[0] / 2) * g.sw[0];
-      // entry words: q, -2 c_i (ND), mu_c (C), entry index
-      constexpr int EW = 2 + ND + C;
-      auto load = [&](int l, float* R) {
-        const float* src = L.rrec[vwave][l];
-        if constexpr (EW == 6) {
-          const float4 r0 = *reinterpret_cast<const float4*>(src);
-          const float2 r1 = *reinterpret_cast<const float2*>(src + 4);
-          R[0] = r0.x; R[1] = r0.y; R[2] = r0.z; R[3] = r0.w; R[4] = r1.x; R[5] = r1.y;
-        } else {
+    // this lane's voxel in each block of the row: its channels, its axis-0
+    // term, and the best distance and entry so far
+    const int nbx = min(BXN, (rhi[0] + SH::B[0]) / SH::B[0]);  // blocks in the image
+    float Iv[BXN][C], X0[BXN], bD[BXN];
+    int bE[BXN];
+#pragma unroll
+    for (int bx = 0; bx < BXN; ++bx) {
+      const int x = bx * SH::B[0] + lx[0];
+      // lanes past the image's edge (last block only) read its last voxel
+      const T* px = prow + (uint32_t)min(x, rhi[0]) * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) Iv[bx][c] = bx < nbx ? (float)px[c] : 0.0f;
+      X0[bx] = (float)(x - SH::T[0] / 2) * g.sw[0];
+      bD[bx] = __builtin_inff();
+      bE[bx] = -1;
+    }
+
+    // The held entries one at a time, in ascending table order: the terms of
+    // axes 1 and 2 once, then each block of the row the window meets.  On
+    // such a block the window is applied as a lane mask (its axis-0 bits for
+    // the block, repeated over the block's 16 lines, and its part along
+    // axes 1 and 2; all lanes when it covers the block); lanes outside it
+    // see an infinite distance.  The compare is strict, so equal distances
+    // keep the earlier entry, i.e. the lowest cluster index.
+    constexpr int EW = 2 + ND + C;  // entry words: q, -2 c_i (ND), mu_c (C), entry index
+    constexpr uint32_t kFull = (1u << SH::B[0]) - 1u;
+    auto walk = [&]() {
+      uint64_t m = hm;
+      while (m) {
+        const int j = (int)__builtin_ctzll(m);
+        m = clear_bit(m, j);
+        const uint32_t xb = (uint32_t)__builtin_amdgcn_readlane((int)xb0, j);
+        const uint32_t yzl = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)myz, j);
+        const uint32_t yzh = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(myz >> 32), j);
+        float R[EW];
+        {
+          const float* src = L.rrec[vwave][j];
           const float4 r0 = *reinterpret_cast<const float4*>(src);
           const float4 r1 = *reinterpret_cast<const float4*>(src + 4);
           const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
 #pragma unroll
           for (int w = 0; w < EW; ++w) R[w] = rr[w];
         }
-      };
-      auto one = [&](const float* R, auto masked, uint64_t wm) {
-        float D = fmaf(x0, R[1], R[0]);
+        float P = R[0];
 #pragma unroll
-        for (int i = 1; i < ND; ++i) D = fmaf(xs[i], R[1 + i], D);
+        for (int i = 1; i < ND; ++i) P = fmaf(xs[i], R[1 + i], P);
+        const int rk = __float_as_int(R[EW - 1]);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const float t = Iv[c] - R[1 + ND + c];
-          D = fmaf(t, t, D);
+        for (int bx = 0; bx < BXN; ++bx) {
+          const uint32_t nib = (xb >> (bx * SH::B[0])) & kFull;
+          if (nib == 0u) continue;
+          const uint32_t p = nib * 0x11111111u;
+          const uint64_t mk = (uint64_t)(p & yzh) << 32 | (p & yzl);
+          float D = fmaf(X0[bx], R[1], P);
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const float t = Iv[bx][c] - R[1 + ND + c];
+            D = fmaf(t, t, D);
+          }
+          D = __builtin_amdgcn_inverse_ballot_w64(mk) ? D : __builtin_inff();
+          const bool cm = D < bD[bx];
+          bD[bx] = cm ? D : bD[bx];
+          bE[bx] = cm ? rk : bE[bx];
         }
-        const uint32_t khi = __float_as_uint(D), klo = (uint32_t)__float_as_int(R[EW - 1]);
-        bool c = ((uint64_t)khi << 32 | klo) < ((uint64_t)kbh << 32 | kbl);
-        if constexpr (decltype(masked)::value) c = c & __builtin_amdgcn_inverse_ballot_w64(wm);
-        kbh = c ? khi : kbh;
-        kbl = c ? klo : kbl;
-      };
-      // the entries of mask m two at a time, both entries' words read before
-      // either is evaluated (an odd last entry is evaluated twice, which
-      // leaves the best key as it is)
-      auto walk = [&](uint64_t m, auto masked) {
-        while (m) {
-          const int l1 = (int)__builtin_ctzll(m);
-          m = clear_bit(m, l1);
-          int l2 = first_bit(m);
-          l2 = l2 < 0 ? l1 : l2;
-          m = clear_bit(m, l2);
-          float R1[EW], R2[EW];
-          load(l1, R1);
-          load(l2, R2);
-          one(R1, masked, decltype(masked)::value ? readlane64(pm, l1) : 0ull);
-          one(R2, masked, decltype(masked)::value ? readlane64(pm, l2) : 0ull);
-        }
-      };
-      walk(Cv, std::false_type{});
-      walk(M & ~Cv, std::true_type{});
+      }
     };
 
-    // The sums of this lane's voxels, added to the table in runs: a run is
-    // this lane's voxels of consecutive blocks of the row with one entry
-    // (2D labels often repeat from one block to the next along axis 0; 3D
-    // ones rarely do, so there a run is one voxel).
-    int run_e = -1;
-    uint32_t run_n = 0, run_x = 0, run_c[C];
+    const int cnt = build(rlo, rhi, 0, std::true_type{});
+    for (int c0 = 0;;) {
+      hold(min(cnt - c0, 64));
+      walk();
+      c0 += 64;
+      if (c0 >= cnt) break;
+      // more than 64 entries meet the row: the next 64
+      __builtin_amdgcn_wave_barrier();
+      build(rlo, rhi, c0, std::true_type{});
+    }
+
+    // no window holds this voxel: its grid cell (first iteration) or its
+    // previous label, summed straight into the accumulators
+    auto uncovered = [&](int x, const float* Ivc) {
+      int xa[ND];
+      xa[0] = to[0] + x;
+      for (int i = 1; i < ND; ++i) xa[i] = to[i] + rlo[i] + lx[i];
+      int64_t lin = 0;
+      for (int i = 0; i < ND; ++i) lin += (int64_t)xa[i] * g.st[i];
+      const int lab = iter == 0 ? grid_label(g, xa, ND) : a.labels[lin];
+      a.accf[lab] = 1;
+      unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)lab * F);
+      atomicAdd(gg, 1ull);
+      for (int i = 0; i < ND; ++i) atomicAdd(gg + 1 + i, (unsigned long long)xa[i]);
+      for (int c = 0; c < C; ++c) atomicAdd(gg + 1 + ND + c, (unsigned long long)Ivc[c]);
+      return lab;
+    };
+
+    // labels and sums of this lane's voxels; the rare ones no window holds
+    // afterwards, one at a time
+    uint32_t unc = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) run_c[c] = 0;
-    auto flush = [&]() {
-      if (run_e < 0) return;
+    for (int bx = 0; bx < BXN; ++bx) {
+      const int x = bx * SH::B[0] + lx[0];
+      if (bx >= nbx || !rowok || x > rhi[0]) continue;
+      const int e = bE[bx];
+      if (e < 0) {
+        unc |= 1u << bx;
+        continue;
+      }
       uint32_t v[PK::kFields];
-      v[0] = run_n;
-      v[1] = run_x;
-      for (int i = 1; i < ND; ++i) v[1 + i] = run_n * (uint32_t)(rlo[i] + lx[i]);
+      v[0] = 1;
+      v[1] = (uint32_t)x;
+      for (int i = 1; i < ND; ++i) v[1 + i] = (uint32_t)(rlo[i] + lx[i]);
 #pragma unroll
-      for (int c = 0; c < C; ++c) v[1 + ND + c] = run_c[c];
+      for (int c = 0; c < C; ++c) v[1 + ND + c] = (uint32_t)Iv[bx][c];
       uint64_t pw[NW];
       pack_run<PK>(v, pw);
 #pragma unroll
-      for (int w = 0; w < NW; ++w)
-        atomicAdd(&L.sum[lane & (SH::kRep - 1)][run_e][w], (unsigned long long)pw[w]);
-      run_e = -1;
-    };
-
-    // label and sums of this lane's voxel of block bx
-    auto finish = [&](int x, const float* Iv, int e) {
-      int lab;
-      if (e >= 0) {
-        lab = L.kk[e];
-        if constexpr (SH::kRuns) {
-          if (e != run_e) {
-            flush();
-            run_e = e;
-            run_n = 0;
-            run_x = 0;
-#pragma unroll
-            for (int c = 0; c < C; ++c) run_c[c] = 0;
-          }
-          ++run_n;
-          run_x += (uint32_t)x;
-#pragma unroll
-          for (int c = 0; c < C; ++c) run_c[c] += (uint32_t)Iv[c];
-        } else {
-          run_e = e;
-          run_n = 1;
-          run_x = (uint32_t)x;
-#pragma unroll
-          for (int c = 0; c < C; ++c) run_c[c] = (uint32_t)Iv[c];
-          flush();
-        }
-      } else {
-        // no window holds this voxel: its grid cell (first iteration) or
-        // its previous label, summed straight into the accumulators
-        int xa[ND];
-        xa[0] = to[0] + x;
-        for (int i = 1; i < ND; ++i) xa[i] = to[i] + rlo[i] + lx[i];
-        int64_t lin = 0;
-        for (int i = 0; i < ND; ++i) lin += (int64_t)xa[i] * g.st[i];
-        lab = iter == 0 ? grid_label(g, xa, ND) : a.labels[lin];
-        a.accf[lab] = 1;
-        unsigned long long* gg = reinterpret_cast<unsigned long long*>(a.acc + (int64_t)lab * F);
-        atomicAdd(gg, 1ull);
-        for (int i = 0; i < ND; ++i) atomicAdd(gg + 1 + i, (unsigned long long)xa[i]);
-        for (int c = 0; c < C; ++c) atomicAdd(gg + 1 + ND + c, (unsigned long long)Iv[c]);
-      }
-      L.lab[wave][lbase + x] = lab;
-    };
-
-    // one block of the row: its voxels, their best entries, labels and sums
-    auto block = [&](int bx, auto slow) {
-      const int xlo = bx * SH::B[0];
-      const int xhi = min(xlo + SH::B[0] - 1, rhi[0]);
-      const int x = xlo + lx[0];
-      float Iv[C];
-      {
-        // lanes past the image's edge (last block only) read its last voxel
-        const T* px = prow + (uint32_t)min(x, rhi[0]) * C;
-#pragma unroll
-        for (int c = 0; c < C; ++c) Iv[c] = (float)px[c];
-      }
-      uint32_t kbh = ~0u, kbl = ~0u;  // best key: none yet
-      if constexpr (!decltype(slow)::value) {
-        eval(xlo, xhi, Iv, kbh, kbl);
-      } else {
-        // more than 64 entries meet the row: per block, 64 at a time
-        int bl[ND], bh[ND];
-        bl[0] = xlo;
-        bh[0] = xhi;
-        for (int i = 1; i < ND; ++i) {
-          bl[i] = rlo[i];
-          bh[i] = rhi[i];
-        }
-        for (int c0 = 0;; c0 += 64) {
-          const int bc = build(bl, bh, c0, std::false_type{});
-          hold(min(bc - c0, 64));
-          eval(xlo, xhi, Iv, kbh, kbl);
-          if (c0 + 64 >= bc) break;
-        }
-      }
-      if (rowok && x <= rhi[0]) finish(x, Iv, kbh == ~0u ? -1 : (int)kbl);
-    };
-
-    const int nbx = min(BXN, (rhi[0] + SH::B[0]) / SH::B[0]);  // blocks in the image
-    const int cnt = build(rlo, rhi, 0, std::true_type{});
-    if (cnt <= 64) {
-      hold(cnt);
-#pragma unroll 1
-      for (int bx = 0; bx < nbx; ++bx) block(bx, std::false_type{});
-    } else {
-#pragma unroll 1
-      for (int bx = 0; bx < nbx; ++bx) block(bx, std::true_type{});
+      for (int w = 0; w < NW; ++w) atomicAdd(&L.sum[lane & (SH::kRep - 1)][e][w], (unsigned long long)pw[w]);
+      L.lab[wave][lbase + x] = L.kk[e];
     }
-    flush();
+    while (unc) {
+      const int bx = (int)__builtin_ctz(unc);
+      unc &= unc - 1;
+      const int x = bx * SH::B[0] + lx[0];
+      float Ivc[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) Ivc[c] = (float)prow[(uint32_t)x * C + c];
+      L.lab[wave][lbase + x] = uncovered(x, Ivc);
+    }
     __builtin_amdgcn_wave_barrier();
     // the row's labels, four per store along axis 0
     constexpr int Q = SH::T[0] / 4;  // stores per line
