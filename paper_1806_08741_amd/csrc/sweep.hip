@@ -814,7 +814,7 @@ struct FastLds {
   // to copy l mod kRep, so lanes of one label meet at one address less often
   unsigned long long sum[SH::kRep][SH::kTab][NW];
   union alignas(16) {
-    float rrec[kWaves][64][8];  // per wave: the entries of the current row
+    int rl[kWaves][64];  // per wave: the table index of each entry of the current row
     int tk[SH::kTab];           // while building: cluster of each unranked entry
   };
   union alignas(16) {
@@ -1019,9 +1019,6 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       r /= SH::B[i];
     }
   }
-  // the wave's index kept in a vector register, so that addresses into its
-  // row list are formed by one vector add rather than scalar arithmetic
-  const int vwave = (int)(threadIdx.x >> 6);
 
   // Copies the table entries meeting the box [blo, bhi] (tile-relative) that
   // sit at positions [c0, c0 + 64) of its list into the wave's list; returns
@@ -1052,13 +1049,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       }
       const uint64_t bal = __ballot(m);
       const int p = cnt + lanes_below(bal) - c0;
-      if (m && p >= 0 && p < 64) {
-        const float4* src = reinterpret_cast<const float4*>(L.rec[e]);
-        const float4 a0 = src[0], a1 = src[1];
-        float4* dst = reinterpret_cast<float4*>(L.rrec[wave][p]);
-        dst[0] = a0;
-        dst[1] = a1;
-      }
+      if (m && p >= 0 && p < 64) L.rl[wave][p] = e;
       cnt += (int)__popcll(bal);
     }
     __builtin_amdgcn_wave_barrier();
@@ -1098,12 +1089,13 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
     // entry j, its window bounds, the part of its lane mask along axes 1 and
     // 2, and its coverage of the row's axis-0 positions.
     bool held = false;
+    int ej = 0;  // table index of the held entry
     int lo[ND], hi[ND];
     uint64_t myz = 0, hm = 0;
     uint32_t xb0 = 0;  // axis-0 positions of the row (tile-relative) in the window
     auto hold = [&](int nc) {
       held = lane < nc;
-      const int ej = held ? __float_as_int(L.rrec[wave][lane][1 + ND + C]) : 0;
+      ej = held ? L.rl[wave][lane] : 0;
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
         const uint32_t w = L.tb[i][ej];
@@ -1124,7 +1116,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
     // this lane's voxel in each block of the row: its channels, its axis-0
     // term, and the best distance and entry so far
     const int nbx = min(BXN, (rhi[0] + SH::B[0]) / SH::B[0]);  // blocks in the image
-    float Iv[BXN][C], X0[BXN], bD[BXN];
+    float Iv[BXN][C], bD[BXN];
     int bE[BXN];
 #pragma unroll
     for (int bx = 0; bx < BXN; ++bx) {
@@ -1133,13 +1125,17 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       const T* px = prow + (uint32_t)min(x, rhi[0]) * C;
 #pragma unroll
       for (int c = 0; c < C; ++c) Iv[bx][c] = bx < nbx ? (float)px[c] : 0.0f;
-      X0[bx] = (float)(x - SH::T[0] / 2) * g.sw[0];
       bD[bx] = __builtin_inff();
       bE[bx] = -1;
     }
+    // axis-0 coordinate of this lane's voxel in block 0, and the step from
+    // one block to the next
+    const float x00 = (float)(lx[0] - SH::T[0] / 2) * g.sw[0];
+    const float xstep = (float)SH::B[0] * g.sw[0];
 
     // The held entries one at a time, in ascending table order: the terms of
-    // axes 1 and 2 once, then each block of the row the window meets.  On
+    // axes 1 and 2 and of axis 0 at block 0 once, then each block of the row
+    // the window meets (its axis-0 term a multiple of one step).  On
     // such a block the window is applied as a lane mask (its axis-0 bits for
     // the block, repeated over the block's 16 lines, and its part along
     // axes 1 and 2; all lanes when it covers the block); lanes outside it
@@ -1157,7 +1153,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
         const uint32_t yzh = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(myz >> 32), j);
         float R[EW];
         {
-          const float* src = L.rrec[vwave][j];
+          const float* src = L.rec[__builtin_amdgcn_readlane(ej, j)];
           const float4 r0 = *reinterpret_cast<const float4*>(src);
           const float4 r1 = *reinterpret_cast<const float4*>(src + 4);
           const float rr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
@@ -1167,6 +1163,9 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
         float P = R[0];
 #pragma unroll
         for (int i = 1; i < ND; ++i) P = fmaf(xs[i], R[1 + i], P);
+        // the terms up to the channels at block 0, and their step per block
+        const float Q = fmaf(x00, R[1], P);
+        const float dq = xstep * R[1];
         const int rk = __float_as_int(R[EW - 1]);
 #pragma unroll
         for (int bx = 0; bx < BXN; ++bx) {
@@ -1174,7 +1173,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
           if (nib == 0u) continue;
           const uint32_t p = nib * 0x11111111u;
           const uint64_t mk = (uint64_t)(p & yzh) << 32 | (p & yzl);
-          float D = fmaf(X0[bx], R[1], P);
+          float D = fmaf((float)bx, dq, Q);
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             const float t = Iv[bx][c] - R[1 + ND + c];
