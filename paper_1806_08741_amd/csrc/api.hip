@@ -124,6 +124,7 @@ Layout layout(const Geo& g, int iterations, bool cc, bool part, bool persist) {
     L.cc_newlab = put((size_t)g.N * 4);
     L.cc_part = put((size_t)cc_part_ints(g.N) * 4);
     L.cc_roots = put((size_t)g.N * 4);
+    L.cc_xface = put((size_t)cc_xface_ints(g) * 4);
   }
   L.dist = put(persist ? (size_t)g.N * 4 : 0);
   L.total = o;
@@ -173,6 +174,7 @@ CCBuf cc_view(char* b, const Layout& L, int64_t N) {
   c.newlab = (int32_t*)(b + L.cc_newlab);
   cc_carve(c, (int32_t*)(b + L.cc_part), N);
   c.roots = (int32_t*)(b + L.cc_roots);
+  c.xface = (int32_t*)(b + L.cc_xface);
   c.total = (int32_t*)(b + L.flags) + 2;  // flags: done, iters, total, n_labels
   return c;
 }

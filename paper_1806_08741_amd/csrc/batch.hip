@@ -37,7 +37,7 @@ struct BLayout {
   size_t imgs, cl_img, tile_img, upload_bytes;
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part;
   size_t acc, accf, part, res, flags, nlab;
-  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, total;
+  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, cc_xface, total;
 };
 
 std::array<int, 7> key_of(const Geo& g) {
@@ -193,7 +193,7 @@ struct Plan {
   std::vector<int> ord;       // batch order -> caller's index
   std::vector<Geo> geo;       // by caller's index
   std::vector<Group> groups;
-  int64_t K = 0, nbins = 0, Nmax = 0;
+  int64_t K = 0, nbins = 0, Nmax = 0, XFmax = 0;
   int ntiles = 0, rs = 4;
   BLayout L{};
 };
@@ -266,6 +266,7 @@ int enqueue(sslic_ctx* ctx, const Plan& P, hipStream_t q, bool timed) {
     c.newlab = reinterpret_cast<int32_t*>(b + P.L.cc_newlab);
     cc_carve(c, reinterpret_cast<int32_t*>(b + P.L.cc_part), P.Nmax);
     c.roots = reinterpret_cast<int32_t*>(b + P.L.cc_roots);
+    c.xface = reinterpret_cast<int32_t*>(b + P.L.cc_xface);
     c.total = flags + 2 * P.n + 1;
     int32_t* nlab = reinterpret_cast<int32_t*>(b + P.L.nlab);
     for (int j = 0; j < P.n; ++j) {
@@ -381,6 +382,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
         return fail(SSLIC_EINVAL, "batch too large for 32-bit cluster, bin and tile indices");
       P.ntiles += b.a.ntiles;
       P.Nmax = std::max(P.Nmax, g.N);
+      P.XFmax = std::max(P.XFmax, cc_xface_ints(g));
       b.a.bstart = nullptr;
       acc_w += (size_t)g.K * g.F;  // offsets in words, resolved below
       part_w += b.a.slots ? (size_t)g.K * ((size_t)1 << g.nd) * (g.F + 1) : 0;
@@ -422,6 +424,7 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       L.cc_newlab = put((size_t)P.Nmax * 4);
       L.cc_part = put((size_t)cc_part_ints(P.Nmax) * 4);
       L.cc_roots = put((size_t)P.Nmax * 4);
+      L.cc_xface = put((size_t)P.XFmax * 4);
     }
     L.total = off;
     if ((rc = ensure_bws(ctx, L.total))) return rc;

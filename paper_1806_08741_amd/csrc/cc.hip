@@ -106,6 +106,15 @@ struct CCTile<4> {
 constexpr int kTileVox = 4096;
 constexpr int kSeg = kTileVox / kThreads;  // voxels a thread walks along axis 0
 
+// A tile's first and last column along axis 0 (one voxel per line of the
+// tile, each on a line of memory of its own) are also kept compact, per tile:
+// [0] labels and [1] local roots of the first column, [2] and [3] of the
+// last, so the face unions across axis 0 read them as whole lines.
+template <int ND>
+constexpr int xcol() { return kTileVox >> CCTile<ND>::L[0]; }
+template <int ND>
+constexpr int xface_ints() { return 4 * xcol<ND>(); }
+
 template <int ND>
 __device__ __forceinline__ void tile_origin(const Geo& g, int tile, int* o) {
   int r = tile;
@@ -181,6 +190,8 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   __shared__ int s_par[kPadVox];
   int* s_size = s_lab;
   const TileIndex<ND> ti(g, blockIdx.x);
+  constexpr int XL = CCTile<ND>::L[0], XE = 1 << XL;
+  int32_t* xf = b.xface + (int64_t)blockIdx.x * xface_ints<ND>();
   {
     int lab[kSeg];  // all of this thread's loads in flight at once
 #pragma unroll
@@ -189,6 +200,7 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
       const int v = ti.at(g, threadIdx.x + q * kThreads, in);
       lab[q] = in ? labels[v] : -1;
     }
+
 #pragma unroll
     for (int q = 0; q < kSeg; ++q) {
       const int j = threadIdx.x + q * kThreads;
@@ -197,6 +209,11 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     }
   }
   __syncthreads();
+  // the first and last columns' labels, as whole lines
+  for (int t = threadIdx.x; t < 2 * xcol<ND>(); t += kThreads) {
+    const int c = t / xcol<ND>(), f = t % xcol<ND>();
+    xf[2 * c * xcol<ND>() + f] = s_lab[pd((f << XL) + c * (XE - 1))];
+  }
   // every thread walks kSeg consecutive voxels of one row along axis 0, with
   // their labels in registers (LDS reads issued together, not one per test):
   // runs of equal labels point at their first voxel (no atomics) ...
@@ -312,8 +329,16 @@ cc_local_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     if (r < 0) continue;
     bool in;
     const int v = ti.at(g, j, in);
-    b.parent[v] = ti.at(g, r, in);
+    const int gr = ti.at(g, r, in);
+    b.parent[v] = gr;
     b.size[v] = s_size[pd(j)];  // non-zero exactly at local roots
+  }
+  // the first and last columns' local roots, as whole lines
+  for (int t = threadIdx.x; t < 2 * xcol<ND>(); t += kThreads) {
+    const int c = t / xcol<ND>(), f = t % xcol<ND>();
+    const int j = (f << XL) + c * (XE - 1), r = s_par[pd(j)];
+    bool in;
+    xf[(2 * c + 1) * xcol<ND>() + f] = r < 0 ? -1 : ti.at(g, r, in);
   }
 }
 
@@ -341,6 +366,7 @@ __global__ void __launch_bounds__(kThreads)
 cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
   const TileIndex<ND> ti(g, blockIdx.x);
   constexpr int K = Faces<ND>::kItems;
+  const int32_t* xf = b.xface + (int64_t)blockIdx.x * xface_ints<ND>();
   int v[K], u[K], lv[K], lu[K], ax[K], f[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -366,8 +392,15 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
     f[k] = F;
     v[k] = vi;
     u[k] = vi - du;
-    lv[k] = in ? labels[vi] : -1;
-    lu[k] = in ? labels[vi - du] : -2;
+    if (i == 0) {
+      // across axis 0: this tile's first column and the last of the tile
+      // before it, from their compact copies
+      lv[k] = in ? xf[F] : -1;
+      lu[k] = in ? xf[2 * xcol<ND>() - xface_ints<ND>() + F] : -2;
+    } else {
+      lv[k] = in ? labels[vi] : -1;
+      lu[k] = in ? labels[vi - du] : -2;
+    }
   }
   uint32_t need = 0;
 #pragma unroll
@@ -383,8 +416,13 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const bool n = need & (1u << k);
-    pa[k] = n ? b.parent[u[k]] : 0;
-    pb[k] = n ? b.parent[v[k]] : 0;
+    if (ax[k] == 0) {
+      pa[k] = n ? xf[3 * xcol<ND>() - xface_ints<ND>() + f[k]] : 0;
+      pb[k] = n ? xf[xcol<ND>() + f[k]] : 0;
+    } else {
+      pa[k] = n ? b.parent[u[k]] : 0;
+      pb[k] = n ? b.parent[v[k]] : 0;
+    }
   }
   while (need) {
     const int k = (int)__builtin_ctz(need);
@@ -761,6 +799,16 @@ cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, int32_t* n_label
 }
 
 }  // namespace
+
+int64_t cc_xface_ints(const Geo& g) {
+  int64_t ntiles = 1;
+  for (int i = 0; i < g.nd; ++i) {
+    const int L = g.nd == 2 ? CCTile<2>::L[i] : g.nd == 3 ? CCTile<3>::L[i] : CCTile<4>::L[i];
+    ntiles *= (g.n[i] + (1 << L) - 1) >> L;
+  }
+  const int w = g.nd == 2 ? xface_ints<2>() : g.nd == 3 ? xface_ints<3>() : xface_ints<4>();
+  return ntiles * w;
+}
 
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels, const CCBuf& b,
                                int32_t* n_labels_dev, hipStream_t s) {

@@ -57,7 +57,7 @@ size_t al(size_t v);
 // sections of the single-image workspace
 struct Layout {
   size_t ctab, bin_of, bin_cnt, bin_start, bin_items, scan_part, acc, accf, part, res_acc, flags;
-  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, dist, total;
+  size_t cc_parent, cc_size, cc_newlab, cc_part, cc_roots, cc_xface, dist, total;
 };
 // persist: room for the distance image kept across iterations (f32 [N])
 Layout layout(const Geo& g, int iterations, bool cc, bool part, bool persist = false);

@@ -191,6 +191,8 @@ struct CCBuf {
   int32_t* bpart;     // [ceil(chunks / 4096) + 1] scan partials of part
   int32_t* brpart;    // [ceil(chunks / 4096) + 1] scan partials of rpart
   int32_t* roots;     // [N] the roots in raster order
+  int32_t* xface;     // [tiles][4][tile voxels / tile extent along axis 0]: label and
+                      // local root of each tile's first and last column along axis 0
   int32_t* total;     // [1] number of new labels
   int32_t* nroots;    // [1] number of roots
 };
@@ -214,5 +216,7 @@ hipError_t launch_mask_contours(const Geo& g, const void* img, const int32_t* la
                                 hipStream_t s);
 hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
                                const CCBuf& b, int32_t* n_labels_dev, hipStream_t s);
+// ints of CCBuf::xface for an image
+int64_t cc_xface_ints(const Geo& g);
 
 }  // namespace sslic
