@@ -71,6 +71,7 @@ BImg make_bimg(const Geo& g, int var, const sslic_image_desc& d) {
   b.a.ntiles = tiles_of(g, var, b.a.nt);
   b.a.slots = sweep_slots(g, var);
   b.a.table = sweep_table_suits(g, var);
+  b.a.fast = var == 0;  // as sslic_run: the fast form where it applies, on its tile shape
   sweep_tile_shape(g.nd, b.tdim, var);
   for (int i = g.nd; i < kMaxDim; ++i) b.tdim[i] = 1;
   return b;
@@ -305,11 +306,14 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
   }
   if ((rc = select_device(ctx))) return rc;
 
-  // tile variant per image: tuned once per (ndim, channels, dtype, S)
+  // tile variant per image: tuned once per (ndim, channels, dtype, S); the
+  // images the fast form serves keep its tile shape, as in sslic_run, so
+  // that a batch gives them the same results as a run of their own
   std::vector<int> var(n, 0);
   if (!o.no_autotune) {
     std::map<std::array<int, 7>, int> pick;
     for (int i = 0; i < n; ++i) {
+      if (sweep_fast_applies(P.geo[i])) continue;
       auto k = key_of(P.geo[i]);
       if (ctx->tune.count(k)) continue;
       auto f = pick.find(k);
@@ -320,7 +324,8 @@ int run_batch(sslic_ctx* ctx, const sslic_image_desc* images, int n, const sslic
       if ((rc = autotune(ctx, images[kv.second], P.geo[kv.second], s, &v))) return rc;
       ctx->tune[kv.first] = v;
     }
-    for (int i = 0; i < n; ++i) var[i] = ctx->tune[key_of(P.geo[i])];
+    for (int i = 0; i < n; ++i)
+      var[i] = sweep_fast_applies(P.geo[i]) ? 0 : ctx->tune[key_of(P.geo[i])];
   }
 
   // what a captured graph would have been made for

@@ -123,6 +123,8 @@ hipError_t launch_sweep(const Geo& g, const void* img, const Iter& it, int32_t* 
                         int iter, int accumulate, hipStream_t s, int var = 0);
 constexpr int kTileVars = 2;
 int sweep_slots(const Geo& g, int var = 0);          // whether the sweep uses tile slots
+// whether the sweep tries its fast form on image g (on the default tile shape)
+bool sweep_fast_applies(const Geo& g);
 void sweep_tile_shape(int nd, int* T, int var = 0);  // its tile extent per axis
 
 // ---- batched form ----------------------------------------------------------

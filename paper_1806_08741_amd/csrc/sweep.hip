@@ -983,7 +983,9 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
 #pragma unroll
     for (int c = 0; c < C; ++c) R[1 + ND + c] = rec[c];
     R[1 + ND + C] = __int_as_float(rank);
-    L.kk[rank] = k;
+    // the image's own cluster index, from the record (a batch shares one
+    // record table: k there counts across its images)
+    L.kk[rank] = irec[rec_k(C, ND)];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       const int lo = min(max(irec[rec_lo(C, ND) + i] - to[i], -1), SH::T[i]);
@@ -1392,7 +1394,12 @@ __global__ void __launch_bounds__(kThreads)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
                    int ntiles, const int32_t* __restrict__ bin_start,
                    const int32_t* __restrict__ items, const float* __restrict__ recs, int iter) {
-  __shared__ SweepLds<T, ND, CC, SH> L;
+  constexpr bool kFast = fast_ok<T, ND, CC>() && std::is_same<SH, Shape<ND, 0>>::value;
+  using LF = typename std::conditional<kFast, FastLds<T, ND, CC>, char>::type;
+  __shared__ union {
+    LF f;
+    SweepLds<T, ND, CC, SH> s;
+  } L;
   const int xcd = (int)(blockIdx.x % 8), per = (int)(gridDim.x / 8);
   const int chunk = (ntiles + 7) / 8;
   const int end = min((xcd + 1) * chunk, ntiles);
@@ -1400,8 +1407,17 @@ sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ ti
     const BImg& d = imgs[tile_img[tile0 + t]];
     if (d.flags[0]) continue;
     __syncthreads();  // the previous tile's table is read out
-    sweep_tile_acc<T, ND, CC, SH>(d.g, reinterpret_cast<const T*>(d.img), bin_start + d.binoff,
-                                  items, recs, d.a, iter, tile0 + t - d.tile_off, L);
+    const T* img = reinterpret_cast<const T*>(d.img);
+    const int tile = tile0 + t - d.tile_off;
+    if constexpr (kFast) {
+      // the same form sslic_run takes for this image, so the results agree
+      if (d.a.fast && sweep_tile_fast<T, ND, CC>(d.g, img, bin_start + d.binoff, items, recs, d.a,
+                                                 iter, tile, L.f))
+        continue;
+      __syncthreads();  // the fast form's reads of its table are done
+    }
+    sweep_tile_acc<T, ND, CC, SH>(d.g, img, bin_start + d.binoff, items, recs, d.a, iter, tile,
+                                  L.s);
   }
 }
 
@@ -1497,6 +1513,11 @@ void sweep_tile_shape(int nd, int* T, int var) {
   if (nd == 2) shape_of<2>(var, T);
   else if (nd == 3) shape_of<3>(var, T);
   else shape_of<4>(var, T);
+}
+
+bool sweep_fast_applies(const Geo& g) {
+  // as fast_ok: integer pixels, 3 axes, 1 + axes + channels <= 7
+  return g.dtype != kF32 && g.nd == 3 && g.C > 0 && 1 + g.nd + g.C <= 7;
 }
 
 int sweep_slots(const Geo& g, int var) {

@@ -66,6 +66,11 @@ def mixed_items():
                       iterations=4))
     items.append(dict(image=rand_image((96, 96), 3, torch.uint8, 6), S=(16, 16), m=10.0,
                       iterations=2))
+    # 3D integer images with few channels: the sweep's fast form, in the batch as alone
+    items.append(dict(image=rand_image((70, 45, 38), 1, torch.uint16, 7), S=(8, 8, 8), m=20.0,
+                      iterations=3))
+    items.append(dict(image=rand_image((48, 40, 36), 3, torch.uint8, 8), S=(8, 8, 8), m=10.0,
+                      iterations=2))
     return items
 
 
