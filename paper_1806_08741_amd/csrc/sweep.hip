@@ -763,15 +763,16 @@ __device__ __forceinline__ bool sweep_tile(const Geo& g, const T* __restrict__ i
 // is the same for every centre a voxel compares, so the argmin is that of
 // D^2.  Each wave then sweeps rows of blocks (8 blocks of 4x4x4 voxels
 // along axis 0, one voxel per lane, each lane holding its 8 voxels of the
-// row): the entries meeting the row are copied to the wave's row list, and
-// the wave walks that list once, entry by entry with its terms read from
-// LDS as wave-uniform values.  An entry's terms along axes 1 and 2 are
-// summed once for the row; each block its window meets then costs one FMA
-// for axis 0, two operations per channel, a compare and two selects.  A
-// window that covers only part of a block is applied as a lane mask (formed
-// in scalar registers from the entry's coverage bits).  Because the list is
-// in ascending cluster index and the compare is strict, equal distances go
-// to the lowest index.
+// row): the table indices of the entries meeting the row form the wave's
+// row list, and the wave walks that list once, entry by entry with its
+// terms read from the table as wave-uniform values.  An entry's terms along
+// axes 1 and 2, and along axis 0 at the row's first block, are summed once
+// for the row; each block its window meets then costs one FMA for axis 0
+// (a multiple of one per-entry step), two operations per channel, a select
+// that gives lanes outside the window an infinite distance, a compare and
+// two selects.  The lane mask is formed in scalar registers from the
+// entry's coverage bits.  Because the list is in ascending cluster index
+// and the compare is strict, equal distances go to the lowest index.
 //
 // Map step: every voxel adds its packed [1, x - o, I] to its winner's table
 // entry with LDS atomics (no per-lane runs, no hashing: the winner's entry
@@ -790,10 +791,10 @@ struct Fast<3> {
   static constexpr int kRep = 1;        // copies of the sums (lanes alternate between them)
 };
 
-// Where the fast form is used: 3D integer images with 1 to 3 channels.  (An
-// earlier 2D variant of it measured slower than the general form, whose
-// candidates are scalar loads rather than LDS reads: 1.54-1.57 against
-// 1.40 ms on the 16384^2 slide.)
+// Where the fast form is used: 3D integer images with 1 to 3 channels.  (Its
+// 2D variants measured slower than the general form on the 16384^2 slide,
+// 1.40 ms: block by block 1.54-1.57 ms, and as this row walk on 64x64 tiles
+// 2.18 ms, a tile of 64 blocks paying for a whole table.)
 template <typename T, int ND, int CC>
 constexpr bool fast_ok() {
   return !std::is_same<T, float>::value && ND == 3 && CC > 0 && 1 + ND + CC <= 7;
@@ -838,11 +839,6 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 __device__ __forceinline__ uint64_t bit_range(int a, int b) {
   const uint64_t r = (~0ull >> (63 - b)) & (~0ull << a);
   return b < a ? 0ull : r;
-}
-
-// bits [a, a + w) of a 32-bit word; w in [0, 8], a in [0, 8]
-__device__ __forceinline__ uint32_t bit_field(int w, int a) {
-  return ((1u << w) - 1u) << a;
 }
 
 // v with bit l cleared, one scalar instruction
