@@ -581,8 +581,9 @@ cc_first_kernel(Geo g, const double* __restrict__ cen, const int32_t* __restrict
 }
 
 
-// Wave w of block x ranks chunk c = 4x + w: voxels [1024 c, 1024 c + 1024)
-// as 16 coalesced rows of 64, in raster order.
+// Wave w of the workgroup numbered x (XCD-ordered, as xcd_block) ranks chunk
+// c = 4x + w: voxels [1024 c, 1024 c + 1024) as 16 coalesced rows of 64, in
+// raster order.
 __device__ __forceinline__ int64_t wave_chunk() {
   return (int64_t)xcd_block() * kWaves + threadIdx.x / 64;
 }
@@ -744,9 +745,11 @@ cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b, int64_
   }
 }
 
-// Small roots take the label their link leads to (most links end at once:
-// the neighbour before a small root usually lies in a large or final
-// component).  The root list is cut into units of 1024 consecutive roots,
+// Small roots take the label their link leads to.  On a fragmented volume a
+// link most often leads to the root just before in raster order (fragments
+// chain back along the rows) and chains run to tens of links; shortcuts come
+// from entries already resolved on the way.  The root list is cut into units
+// of 1024 consecutive roots,
 // and each XCD walks one contiguous eighth of the units in order: a link
 // leads a few rows back, to roots its own XCD has just resolved.  Each
 // thread follows four chains 256 roots apart.  Every root's entry is written
