@@ -8,11 +8,13 @@ oracle's update is fed the GPU's labels after T iterations and the GPU's
 centres after T-1, which are exactly the inputs of the GPU's last update, and
 its result is compared with the GPU's centres, counts and residual after T.
 The cases reach every form of the sweep's map step: the table form (2D, S
->= 12), the hashed form (2D at S = 8, 3D at S = 8), the form without tile
-slots, whose sums all go through 64-bit atomics (a window wider than a tile:
-the paper's own 2D setting S = 50, m = 10 on a 2048 x 1216 three-channel
-float image with CIE-Lab-range values, and 3D at S = 16), 1D, 4D, five
-channels and float images with one and two channels.
+>= 12), the hashed form (2D at S = 8), the fast form of 3D integer images
+(grey and RGB at S = 8, and at S = (2, 16, 16), where a row of blocks is met
+by more than 64 table entries and is walked 64 at a time), the form without
+tile slots, whose sums all go through 64-bit atomics (a window wider than a
+tile: the paper's own 2D setting S = 50, m = 10 on a 2048 x 1216
+three-channel float image with CIE-Lab-range values, and 3D at S = 16), 1D,
+4D, five channels and float images with one and two channels.
 
 Bars: counts and coordinate sums are exact integers, so counts are equal and
 centres of integer images bit-exact; float channel means within 1e-6
@@ -71,7 +73,9 @@ CASES = [
     ("slide-16k", (1000, 777), (16, 16), 10.0, 3, "table"),
     ("rgb-256", (256, 256), (16, 16), 10.0, 10, "table"),
     ("rgb-256", (300, 211), (8, 8), 10.0, 3, "hashed"),
-    ("fibsem-1k", (90, 77, 65), (8, 8, 8), 20.0, 3, "hashed"),
+    ("fibsem-1k", (90, 77, 65), (8, 8, 8), 20.0, 3, "3D fast"),
+    ("rand-u8-3d", (50, 40, 30), (8, 8, 8), 10.0, 3, "3D fast RGB"),
+    ("rand-u16-3d", (60, 48, 40), (2, 16, 16), 10.0, 2, "3D fast long rows"),
     ("lab-2k", (2048, 1216), (50, 50), 10.0, 5, "no slots"),
     ("fibsem-1k", (100, 90, 70), (16, 16, 16), 20.0, 3, "no slots"),
     ("rand-u16-1d", (3001,), (16,), 10.0, 3, "1D"),
@@ -110,8 +114,12 @@ def test_run_update_against_oracle(ctx, name, dims, S, m, T, form):
         assert got_e == pytest.approx(exp_e, rel=1e-9)
 
 
-@pytest.mark.parametrize("name,dims,S,m,T,form", [CASES[0], CASES[3], CASES[4]],
-                         ids=["table", "hashed-3d", "no-slots-lab"])
+# the first case of the table form, of the 3D fast form and without tile slots
+MEANS_CASES = [next(c for c in CASES if c[5] == f) for f in ("table", "3D fast", "no slots")]
+
+
+@pytest.mark.parametrize("name,dims,S,m,T,form", MEANS_CASES,
+                         ids=[f"{c[0]}-{c[5]}" for c in MEANS_CASES])
 def test_run_centres_are_member_means(ctx, name, dims, S, m, T, form):
     """With connectivity off every non-empty cluster's centre is the mean of
     its members: the oracle's update of the GPU's final labels, started from
