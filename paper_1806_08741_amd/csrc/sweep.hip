@@ -1352,8 +1352,11 @@ __device__ __forceinline__ void sweep_tile_acc(const Geo& g, const T* img, const
                                          L.tb, &L.n);
 }
 
+// The fast form's grey instantiations are held to 5 workgroups per CU (at
+// most 102 VGPRs): u8 would otherwise need one register more than 5 waves
+// per SIMD allow, and the walk's latency wants the fifth wave.
 template <typename T, int ND, int CC, bool ACC>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, (ACC && fast_ok<T, ND, CC>() && CC == 1) ? 5 : 1)
 sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
              const int32_t* __restrict__ items, const float* __restrict__ recs, SweepArgs a) {
   if (*a.done) return;
