@@ -781,23 +781,27 @@ __global__ void __launch_bounds__(kThreads) cc_resolve_kernel(CCBuf b) {
   }
 }
 
-// Every voxel takes the label of its component's root; four voxels 256
-// apart per thread, their gathers in flight together.
-constexpr int kRelabelPer = 4;
+// Every voxel takes the label of its component's root, tile by tile (the
+// tiles of the local union-find): the root of a fragment lies in or near its
+// tile, so a tile's gathers fall on a few lines, where raster order would
+// reach planes back for them.  Each thread's 16 gathers are in flight at
+// once.
+template <int ND>
 __global__ void __launch_bounds__(kThreads)
 cc_relabel_kernel(Geo g, int32_t* __restrict__ labels, CCBuf b, int32_t* n_labels) {
-  const int64_t v0 = (int64_t)xcd_block() * (kThreads * kRelabelPer) + threadIdx.x;
-  int p[kRelabelPer];
+  const TileIndex<ND> ti(g, blockIdx.x);
+  int v[kSeg], p[kSeg];
 #pragma unroll
-  for (int k = 0; k < kRelabelPer; ++k) {
-    const int64_t v = v0 + k * kThreads;
-    p[k] = v < g.N ? b.parent[v] : 0;
+  for (int q = 0; q < kSeg; ++q) {
+    bool in;
+    v[q] = ti.at(g, threadIdx.x + q * kThreads, in);
+    p[q] = in ? b.parent[v[q]] : -1;
   }
 #pragma unroll
-  for (int k = 0; k < kRelabelPer; ++k) {
-    const int64_t v = v0 + k * kThreads;
-    if (v < g.N) labels[v] = b.newlab[p[k]];
-  }
+  for (int q = 0; q < kSeg; ++q) p[q] = p[q] >= 0 ? b.newlab[p[q]] : -1;
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q)
+    if (p[q] >= 0) labels[v[q]] = p[q];
   if (n_labels && blockIdx.x == 0 && threadIdx.x == 0) *n_labels = (int32_t)(g.K + *b.total);
 }
 
@@ -848,8 +852,11 @@ hipError_t launch_connectivity(const Geo& g, const double* cen, int32_t* labels,
   cc_root_labels_kernel<<<nwg, kThreads, 0, s>>>(g, labels, b, nchunks);
   const int64_t units = (g.N + 4 * kThreads - 1) / (4 * kThreads);
   cc_resolve_kernel<<<(int)((std::min<int64_t>(units, 1 << 16) + 7) / 8 * 8), kThreads, 0, s>>>(b);
-  cc_relabel_kernel<<<(int)((g.N + kThreads * kRelabelPer - 1) / (kThreads * kRelabelPer)), kThreads,
-                      0, s>>>(g, labels, b, n_labels_dev);
+  switch (g.nd) {
+    case 2: cc_relabel_kernel<2><<<ntiles, kThreads, 0, s>>>(g, labels, b, n_labels_dev); break;
+    case 3: cc_relabel_kernel<3><<<ntiles, kThreads, 0, s>>>(g, labels, b, n_labels_dev); break;
+    default: cc_relabel_kernel<4><<<ntiles, kThreads, 0, s>>>(g, labels, b, n_labels_dev); break;
+  }
   return hipGetLastError();
 }
 
