@@ -444,64 +444,73 @@ cc_faces_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b) {
 // tile points at a local root of the tile, whose global root it then takes
 // from LDS.
 template <int ND>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 5)
 cc_flatten_kernel(Geo g, CCBuf b) {
   __shared__ int s_root[kTileVox];  // global root, at the local roots' entries
   const TileIndex<ND> ti(g, xcd_block());
   float inv[ND];
   for (int i = 0; i < ND; ++i) inv[i] = 1.0f / (float)ti.st[i];
-  int sz[kSeg], par[kSeg], vq[kSeg];  // all of this thread's loads in flight at once
-  uint32_t inm = 0, lr = 0;           // bit q: inside the image / a local root
+  // parents, sizes and indices of this thread's voxels, all loads in flight at
+  // once; cur[q] then walks a linked local root's chain and otherwise stays
+  // the voxel's parent
+  int sz[kSeg], cur[kSeg], vq[kSeg];
+  uint32_t inm = 0, lr = 0, lk = 0;  // bit q: inside the image / a local root / one linked
 #pragma unroll
   for (int q = 0; q < kSeg; ++q) {
     bool in;
     vq[q] = ti.at(g, threadIdx.x + q * kThreads, in);
     sz[q] = in ? b.size[vq[q]] : 0;
-    par[q] = in ? b.parent[vq[q]] : -1;
+    cur[q] = in ? b.parent[vq[q]] : -1;
     inm |= in ? 1u << q : 0u;
   }
 #pragma unroll
-  for (int q = 0; q < kSeg; ++q) lr |= sz[q] > 0 ? 1u << q : 0u;
-  {  // the local roots, one by one (the wave loops as often as its busiest lane)
-    uint32_t m = lr;
-    while (m) {
-      const int q = (int)__builtin_ctz(m);
-      m &= m - 1;
-      int v = vq[0], p = par[0], s = sz[0];
+  for (int q = 0; q < kSeg; ++q) {
+    lr |= sz[q] > 0 ? 1u << q : 0u;
+    lk |= (sz[q] > 0 && cur[q] != vq[q]) ? 1u << q : 0u;
+  }
 #pragma unroll
-      for (int q2 = 1; q2 < kSeg; ++q2) {
-        if (q == q2) {
-          v = vq[q2];
-          p = par[q2];
-          s = sz[q2];
-        }
-      }
-      const int r = p == v ? v : find_root(b.parent, v);
-      s_root[threadIdx.x + q * kThreads] = r;
-      if (r != v) atomicAdd(&b.size[r], s);  // a local root joins its global root
+  for (int q = 0; q < kSeg; ++q)  // the linked roots' sizes wait in their LDS entries
+    if (lk & (1u << q)) s_root[threadIdx.x + q * kThreads] = sz[q];
+  // the linked local roots' chains, all of a thread's a step at a time, until
+  // each reaches a node that is its own parent
+  uint32_t todo = lk;
+  while (todo) {
+    int nx[kSeg];
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) nx[q] = (todo & (1u << q)) ? b.parent[cur[q]] : cur[q];
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) {
+      todo &= nx[q] == cur[q] ? ~(1u << q) : ~0u;
+      cur[q] = nx[q];
     }
+  }
+#pragma unroll
+  for (int q = 0; q < kSeg; ++q) {
+    const int j = threadIdx.x + q * kThreads;
+    if (lk & (1u << q)) atomicAdd(&b.size[cur[q]], s_root[j]);  // a local root joins its global root
+    if (lr & (1u << q)) s_root[j] = cur[q];
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kSeg; ++q) {
     if (!(inm & (1u << q))) continue;
-    const int j = threadIdx.x + q * kThreads;
-    int r;
-    if (lr & (1u << q)) {
-      r = s_root[j];
-    } else {
-      // the local root's tile-local index from its offset to the tile origin
-      // (each quotient is below the tile extent, so the FP32 estimate is off
-      // by at most one)
-      int d = par[q] - ti.base;
+    int r = cur[q];
+    if (!(lr & (1u << q))) {
+      // the local root's tile-local index from its offset to the tile origin:
+      // the FP32 quotient estimate is off by at most one (each quotient is
+      // below the tile extent), and the remainder it leaves lies in
+      // [-stride, 2 stride) and is at most the offset, so it fits in 32 bits
+      int d = cur[q] - ti.base;
       int lj = 0, sh = 0;
       int xq[ND];
       for (int i = ND - 1; i >= 1; --i) {
         int qi = (int)((float)d * inv[i]);
-        if ((int64_t)qi * ti.st[i] > d) --qi;
-        else if ((int64_t)(qi + 1) * ti.st[i] <= d) ++qi;
+        int rem = (int)((uint32_t)d - (uint32_t)qi * (uint32_t)ti.st[i]);
+        const bool lo = rem < 0, hi = rem >= ti.st[i];
+        qi += lo ? -1 : (hi ? 1 : 0);
+        rem += lo ? ti.st[i] : (hi ? -ti.st[i] : 0);
         xq[i] = qi;
-        d -= qi * ti.st[i];
+        d = rem;
       }
       xq[0] = d;
       for (int i = 0; i < ND; ++i) {
