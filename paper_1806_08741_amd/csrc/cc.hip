@@ -721,10 +721,17 @@ cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b, int64_
   int rl = b.part[c], rr = b.rpart[c];
   bool rootq[kRows], largeq[kRows], finq[kRows];
   chunk_roots(g, b, c, rootq, largeq, finq);
+  // axis-0 coordinates from the chunk's first one, one division per chunk:
+  // rows at least a chunk long wrap at most once within it
+  const uint32_t n0 = (uint32_t)g.n[0];
+  const bool one_wrap = n0 >= (uint32_t)kChunk;
+  const uint32_t x0 = one_wrap ? (uint32_t)(c * kChunk) % n0 : 0u;
 #pragma unroll
   for (int q = 0; q < kRows; ++q) {
     const int64_t v = c * kChunk + q * 64 + lane;
     const bool root = rootq[q], large = largeq[q];
+    uint32_t x = x0 + (uint32_t)(q * 64 + lane);
+    x -= x >= n0 ? n0 : 0u;
     const uint64_t mr = __ballot(root), ml = __ballot(large);
     if (root) {
       int lab;
@@ -738,7 +745,7 @@ cc_root_labels_kernel(Geo g, const int32_t* __restrict__ labels, CCBuf b, int64_
         // the face neighbour before v: along the first axis where v is not
         // at the low border (indices fit 32 bits)
         uint32_t r = (uint32_t)v;
-        int64_t pred = -1;
+        int64_t pred = one_wrap && x != 0 ? v - g.st[0] : -1;
         for (int i = 0; i < g.nd && pred < 0; ++i) {
           const uint32_t q2 = r / (uint32_t)g.n[i];
           if (r - q2 * (uint32_t)g.n[i] > 0) pred = v - g.st[i];

@@ -169,8 +169,11 @@ def test_update_arbitrary_labels(ctx):
     np.testing.assert_array_equal(host(got_c), exp_c)
 
 
+# the last two have rows longer than the 1024 voxels one wave ranks, so a
+# wave's voxels wrap to the next row at most once
 CC_CASES = [((64, 48), (8, 8)), ((300, 211), (16, 16)), ((40, 33, 27), (6, 6, 6)),
-            ((500,), (9,)), ((9, 8, 7, 6), (3, 3, 3, 2))]
+            ((500,), (9,)), ((9, 8, 7, 6), (3, 3, 3, 2)),
+            ((1030, 7, 5), (6, 6, 5)), ((1500, 23), (10, 10))]
 
 
 @pytest.mark.parametrize("dims,S", CC_CASES)
