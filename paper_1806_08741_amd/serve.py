@@ -115,16 +115,25 @@ class Server:
 
     def warm(self, reqs: list) -> None:
         """Tile tuning for every (ndim, channels, dtype, S) in ``reqs`` on every
-        lane, on the largest request of each kind (the tuner waits)."""
+        lane, on the largest request of each kind (the tuner waits); then each
+        lane's batch workspace is grown once to what its largest batch can
+        need (as many copies of the request with the largest footprint as the
+        budget admits, up to ``max_batch``), so that no batch while serving
+        grows it: growing frees the old workspace, which waits for the device."""
         kinds = {}
         for r in reqs:
             k = (r.image.dim(), int(r.image.shape[-1]), r.image.dtype, tuple(r.S))
             if k not in kinds or r.voxels > kinds[k].voxels:
                 kinds[k] = r
+        big = max(reqs, key=footprint)
+        nb = max(1, min(self.max_batch, self.max_slots, len(reqs), self.budget // footprint(big)))
         for ctx, st in zip(self.ctxs, self.streams):
             with torch.cuda.stream(st):
                 ctx.run_batch([dict(image=r.image, S=r.S, m=r.m, iterations=1)
                                for r in kinds.values()], tol=self.tol, graph=False)
+                if nb > 1:
+                    ctx.run_batch([dict(image=big.image, S=big.S, m=big.m, iterations=1)] * nb,
+                                  tol=self.tol, graph=False)
         torch.cuda.synchronize()
 
     def _launch(self, lane: int, batch: list) -> None:
