@@ -807,7 +807,7 @@ struct FastLds {
   static constexpr int NW = PK{}.nw;
   alignas(16) float rec[SH::kTab][8];  // q, -2 c_i (ND), mu_c (C), entry index (int bits)
   int kk[SH::kTab];        // cluster index of each entry
-  uint32_t tb[ND][SH::kTab];  // window bounds relative to the tile, (lo + 1) | (hi + 1) << 16
+  uint16_t tb[ND][SH::kTab];  // window bounds relative to the tile, (lo + 1) | (hi + 1) << 8
   // the rows of blocks each entry's window meets: bit b (axis 1) and bit 8 + b
   // (axis 2) for the b-th block along that axis
   uint32_t rb[SH::kTab];
@@ -819,7 +819,7 @@ struct FastLds {
     int tk[SH::kTab];           // while building: cluster of each unranked entry
   };
   union alignas(16) {
-    int lab[kWaves][512];  // per wave: the labels of the current row
+    int lab[kWaves][64 / SH::B[0] / 2 * SH::T[0]];  // per wave: the labels of half the current row's lines
     struct {
       int pre[SH::kBinRows + 1];  // while building: prefix of the bin-row counts
       int rstart[SH::kBinRows];   // and the first item of each bin row
@@ -986,7 +986,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
     for (int i = 0; i < ND; ++i) {
       const int lo = min(max(irec[rec_lo(C, ND) + i] - to[i], -1), SH::T[i]);
       const int hi = min(max(irec[rec_hi(C, ND) + i] - to[i], -1), SH::T[i]);
-      L.tb[i][rank] = (uint32_t)(lo + 1) | (uint32_t)(hi + 1) << 16;
+      L.tb[i][rank] = (uint16_t)((lo + 1) | (hi + 1) << 8);  // both in [0, 33]
     }
     {
       uint32_t rb = 0;
@@ -1041,7 +1041,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
           const uint32_t w = L.tb[i][ec];
-          const int lo = (int)(w & 0xffffu) - 1, hi = (int)(w >> 16) - 1;
+          const int lo = (int)(w & 0xffu) - 1, hi = (int)(w >> 8) - 1;
           m = m & (lo <= bhi[i]) & (hi >= blo[i]);
         }
       }
@@ -1081,7 +1081,8 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       vrow += (int64_t)(to[i] + (rowok ? y : rlo[i])) * g.st[i];
     }
     const T* prow = img + vrow * C;
-    const int lbase = (ND == 2 ? lx[1] * SH::T[0] : (lx[2] * SH::B[1] + lx[1]) * SH::T[0]);
+    // this lane's line of the row (its position along axes 1-2 in the block)
+    const int lline = ND == 2 ? lx[1] : lx[2] * SH::B[1] + lx[1];
 
     // The list (or one 64-entry part of it) the lanes hold: lane j holds
     // entry j, its window bounds, the part of its lane mask along axes 1 and
@@ -1097,8 +1098,8 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
 #pragma unroll
       for (int i = 0; i < ND; ++i) {
         const uint32_t w = L.tb[i][ej];
-        lo[i] = (int)(w & 0xffffu) - 1;
-        hi[i] = (int)(w >> 16) - 1;
+        lo[i] = (int)(w & 0xffu) - 1;
+        hi[i] = (int)(w >> 8) - 1;
       }
       const int a1 = min(max(lo[1] - rlo[1], 0), SH::B[1] - 1);
       const int b1 = max(min(hi[1] - rlo[1], SH::B[1] - 1), 0);
@@ -1213,13 +1214,14 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       return lab;
     };
 
-    // labels and sums of this lane's voxels; the rare ones no window holds
-    // afterwards, one at a time
-    uint32_t unc = 0;
+    // labels and sums of this lane's voxels (the labels replace the entry
+    // indices in bE); the rare voxels no window holds afterwards, one at a time
+    uint32_t unc = 0, own = 0;  // bit bx: voxel bx uncovered / in the image
 #pragma unroll
     for (int bx = 0; bx < BXN; ++bx) {
       const int x = bx * SH::B[0] + lx[0];
       if (bx >= nbx || !rowok || x > rhi[0]) continue;
+      own |= 1u << bx;
       const int e = bE[bx];
       if (e < 0) {
         unc |= 1u << bx;
@@ -1235,7 +1237,7 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       pack_run<PK>(v, pw);
 #pragma unroll
       for (int w = 0; w < NW; ++w) atomicAdd(&L.sum[lane & (SH::kRep - 1)][e][w], (unsigned long long)pw[w]);
-      L.lab[wave][lbase + x] = L.kk[e];
+      bE[bx] = L.kk[e];
     }
     while (unc) {
       const int bx = (int)__builtin_ctz(unc);
@@ -1244,38 +1246,51 @@ __device__ __forceinline__ bool sweep_tile_fast(const Geo& g, const T* __restric
       float Ivc[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) Ivc[c] = (float)prow[(uint32_t)x * C + c];
-      L.lab[wave][lbase + x] = uncovered(x, Ivc);
-    }
-    __builtin_amdgcn_wave_barrier();
-    // the row's labels, four per store along axis 0
-    constexpr int Q = SH::T[0] / 4;  // stores per line
+      const int lab = uncovered(x, Ivc);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int q = lane + 64 * h;
-      const int line = q / Q, x = (q % Q) * 4;
-      int yz[ND];
-      bool ok = x <= rhi[0];
+      for (int b2 = 0; b2 < BXN; ++b2)
+        if (b2 == bx) bE[b2] = lab;
+    }
+    // the row's labels leave half its lines at a time (LDS holds half a row
+    // per wave), staged so that they go out as whole lines, four per store
+    static_assert(BXN == 8 && 64 / SH::B[0] == 16, "a row of 16 lines of 8 blocks' voxels");
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      if ((lline >> 3) == hf) {
+#pragma unroll
+        for (int bx = 0; bx < BXN; ++bx)
+          if (own & (1u << bx)) L.lab[wave][(lline & 7) * SH::T[0] + bx * SH::B[0] + lx[0]] = bE[bx];
+      }
+      __builtin_amdgcn_wave_barrier();
       {
-        int rr = line;
-        for (int i = 1; i < ND; ++i) {
-          yz[i] = rlo[i] + rr % SH::B[i];
-          rr /= SH::B[i];
-          ok = ok && yz[i] <= rhi[i];
+        constexpr int Q = SH::T[0] / 4;  // stores per line
+        const int line = hf * 8 + lane / Q, x = (lane % Q) * 4;
+        int yz[ND];
+        bool ok = x <= rhi[0];
+        {
+          int rr = line;
+          for (int i = 1; i < ND; ++i) {
+            yz[i] = rlo[i] + rr % SH::B[i];
+            rr /= SH::B[i];
+            ok = ok && yz[i] <= rhi[i];
+          }
+        }
+        if (ok) {
+          int64_t lin = to[0] + x;
+          for (int i = 1; i < ND; ++i) lin += (int64_t)(to[i] + yz[i]) * g.st[i];
+          const int4 v = *reinterpret_cast<const int4*>(&L.lab[wave][(lane / Q) * SH::T[0] + x]);
+          int32_t* dst = a.labels + lin;
+          if (x + 3 <= rhi[0] && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+            *reinterpret_cast<int4*>(dst) = v;
+          } else {
+            dst[0] = v.x;
+            if (x + 1 <= rhi[0]) dst[1] = v.y;
+            if (x + 2 <= rhi[0]) dst[2] = v.z;
+            if (x + 3 <= rhi[0]) dst[3] = v.w;
+          }
         }
       }
-      if (!ok) continue;
-      int64_t lin = to[0] + x;
-      for (int i = 1; i < ND; ++i) lin += (int64_t)(to[i] + yz[i]) * g.st[i];
-      const int4 v = *reinterpret_cast<const int4*>(&L.lab[wave][line * SH::T[0] + x]);
-      int32_t* dst = a.labels + lin;
-      if (x + 3 <= rhi[0] && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-        *reinterpret_cast<int4*>(dst) = v;
-      } else {
-        dst[0] = v.x;
-        if (x + 1 <= rhi[0]) dst[1] = v.y;
-        if (x + 2 <= rhi[0]) dst[2] = v.z;
-        if (x + 3 <= rhi[0]) dst[3] = v.w;
-      }
+      if (hf == 0) __builtin_amdgcn_wave_barrier();  // the second half reuses the staging
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1352,11 +1367,14 @@ __device__ __forceinline__ void sweep_tile_acc(const Geo& g, const T* img, const
                                          L.tb, &L.n);
 }
 
-// The fast form's grey instantiations are held to 5 workgroups per CU (at
-// most 102 VGPRs): u8 would otherwise need one register more than 5 waves
-// per SIMD allow, and the walk's latency wants the fifth wave.
+// The fast form's grey instantiations are held to 6 workgroups per CU (at
+// most 80 VGPRs; its LDS, with the window bounds in 16 bits and labels
+// staged half of a row's lines at a time, is 25.2 KB per workgroup): the walk's chains
+// of vector, scalar and vector work are latency-bound, and each further wave
+// per SIMD hides more of it (6.62 -> 6.44 ms from 5 to 6 on the 1024^3
+// volume; a few per-tile values spill to scratch, outside the walk).
 template <typename T, int ND, int CC, bool ACC>
-__global__ void __launch_bounds__(kThreads, (ACC && fast_ok<T, ND, CC>() && CC == 1) ? 5 : 1)
+__global__ void __launch_bounds__(kThreads, (ACC && fast_ok<T, ND, CC>() && CC == 1) ? 6 : 1)
 sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstart,
              const int32_t* __restrict__ items, const float* __restrict__ recs, SweepArgs a) {
   if (*a.done) return;
