@@ -1406,8 +1406,11 @@ sweep_kernel(Geo g, const T* __restrict__ img, const int32_t* __restrict__ bstar
 // robin), so neighbouring tiles of an image share an L2; the workgroups of an
 // XCD stride through its chunk (one tile each when the grid has a workgroup
 // per tile).  Tiles of converged images are skipped.
+// Its grey fast-form instantiations are held to 4 waves per SIMD (127 VGPRs,
+// no spills; 129 and 3 waves unbounded, spills at 5 and 6).
 template <typename T, int ND, int CC, class SH>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, (fast_ok<T, ND, CC>() && CC == 1 &&
+                                             std::is_same<SH, Shape<ND, 0>>::value) ? 4 : 1)
 sweep_batch_kernel(const BImg* __restrict__ imgs, const int32_t* __restrict__ tile_img, int tile0,
                    int ntiles, const int32_t* __restrict__ bin_start,
                    const int32_t* __restrict__ items, const float* __restrict__ recs, int iter) {
